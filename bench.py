@@ -1,0 +1,165 @@
+"""Benchmark of the mesh-distance hot path on one MI355X.
+
+Workload (default): "rings" -- two interlocked tori of 7,502,120 FP32 triangles
+each (2740 x 1369 grid, R = 1, r = 0.1; one mesh handle used twice), B rotated
+about the world z axis by 0.5 degrees per frame, 100 frames.  The tree is
+built once before timing (the meshes are resident in HBM).
+
+A step is one pass of the whole hot path over the 100-frame batch: per query
+the refit of B's tree into A's frame, the persistent traversal with its
+narrow phase, and the FP64 re-evaluation, all 100 queries in one batched
+launch.  value = queries per second over the K timed steps.  Beside it:
+p50 / p99 latency of the same frames issued one query per launch
+(gdist_query, host wall clock including launch and copy-back), the
+roofline of the dominant kernel, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--frames", type=int, default=100)
+    ap.add_argument("--latency-frames", type=int, default=100)
+    ap.add_argument("--cpu-frames", type=int, default=1,
+                    help="Rings frames the CPU oracle baseline evaluates (0 = skip)")
+    ap.add_argument("--nu", type=int, default=2740)
+    ap.add_argument("--nv", type=int, default=1369)
+    ap.add_argument("--no-verify", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import meshgen as g
+    from paper_2411_11244_amd import gdist
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.init()
+    w = g.rings(frames=args.frames, nu=args.nu, nv=args.nv)
+    mesh = w.meshes[0]
+    ctx = gdist.gdist_create(0)
+    h = gdist.gdist_build(ctx, mesh.verts, mesh.tris)
+    info = gdist.gdist_mesh_info(ctx, h)
+    descs = [gdist.make_desc(h, h, q.pose_a, q.pose_b, gdist.GDIST_MIN) for q in w.queries]
+
+    # ---- warmup + timed steps: one batched launch over all frames per step
+    for _ in range(args.warmup):
+        gdist.gdist_query_batch(ctx, descs)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = gdist.gdist_query_batch(ctx, descs)
+        stats.append(gdist.gdist_last_stats(ctx))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    qps = args.frames * args.steps / (t1 - t0)
+
+    # ---- plain form: one query per launch, per-frame latency
+    lat, plain_stats, plain_res = [], [], []
+    for q in w.queries[: args.latency_frames]:
+        ta = time.perf_counter()
+        r = gdist.gdist_query(ctx, h, h, q.pose_a, q.pose_b, gdist.GDIST_MIN)
+        lat.append((time.perf_counter() - ta) * 1e3)
+        plain_stats.append(gdist.gdist_last_stats(ctx))
+        plain_res.append(r)
+    lat = np.array(lat)
+    # batched and plain results agree frame by frame
+    agree = all(a["distance"] == b["distance"] and (a["tri_a"], a["tri_b"]) == (b["tri_a"], b["tri_b"])
+                for a, b in zip(res, plain_res))
+
+    # ---- roofline of the dominant kernel (refit of B's tree, per launch) and
+    # of the traversal, from the library's HIP events on its own stream
+    N, L = info["n_tris"], info["n_leaves"]
+    refit_bytes = 36 * N + 24 * (2 * L - 1)
+    ms_refit = np.mean([s["ms_refit"] for s in plain_stats])
+    ms_trav = np.mean([s["ms_traversal"] for s in plain_stats])
+    refit_gbs = refit_bytes / (ms_refit * 1e-3) / 1e9
+    trav_bytes = np.mean([s["bytes_traversal"] + s["bytes_narrow"] for s in plain_stats])
+    trav_gbs = trav_bytes / (ms_trav * 1e-3) / 1e9
+    dominant = "refit" if ms_refit >= ms_trav else "traversal"
+    roof = {"bound": "hbm", "kernel": "k_refit_leaves+k_reduce_levels (refit of one 7.5M-triangle tree)",
+            "achieved": round(refit_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(refit_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": refit_bytes, "avg_ms_per_launch": round(float(ms_refit), 5)}
+
+    # ---- correctness spot check against the CPU oracle + CPU baseline timing
+    cpu = None
+    verify = None
+    if args.cpu_frames > 0:
+        import oracle
+        oracle.build_oracle(force=False)
+        t = time.perf_counter()
+        refs = []
+        for q in w.queries[: args.cpu_frames]:
+            refs.append(oracle.query(mesh.verts, mesh.tris, g.pose_to_flat(q.pose_a), mesh.verts, mesh.tris,
+                                     g.pose_to_flat(q.pose_b), 0, "bvh"))
+        dt = time.perf_counter() - t
+        cpu = {"value": round(args.cpu_frames / dt, 5), "unit": "queries/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {args.cpu_frames} Rings frame(s), FP64 BVH oracle incl. its tree builds, "
+                         f"single thread, {dt:.1f} s"}
+        if not args.no_verify:
+            errs = [abs(r["distance"] - ref["distance"]) for r, ref in zip(plain_res, refs)]
+            verify = {"frames": len(refs), "max_abs_err": max(errs)}
+
+    out = {
+        "metric": "distance queries/sec at 2x7.5M tris (1 GPU) + p50/p99 latency; HBM GB/s frac",
+        "value": round(qps, 3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "rings", "tris_per_mesh": N, "frames_per_step": args.frames,
+                   "grid": [args.nu, args.nv], "mode": "min", "form": "batched (one launch per step)"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                       "p99": round(float(np.percentile(lat, 99)), 4),
+                       "form": "plain (one query per launch)",
+                       "plain_queries_per_s": round(1e3 / float(np.mean(lat)), 3)},
+        "roofline": roof,
+        "traversal": {"achieved": round(trav_gbs, 1), "unit": "GB/s", "frac": round(trav_gbs / HBM_PEAK_GBS, 4),
+                      "avg_ms": round(float(ms_trav), 5), "algorithmic_bytes": int(trav_bytes)},
+        "dominant_stage": dominant,
+        "stats_last_plain": plain_stats[-1],
+        "batched_equals_plain": agree,
+        "cpu_baseline": cpu,
+        "verify": verify,
+    }
+    print(json.dumps(out))
+    gdist.gdist_destroy(ctx)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * gdist: exact minimum / maximum distance between two rigidly posed triangle
+ * meshes on an AMD Instinct MI355X (gfx950).  C ABI of libgdist.so.
+ *
+ * What is computed (gDist, Fan et al. 2024, Sec. 3, Eqs. 1-2):
+ *   D_min = min over p in A, q in B of |p - q|,   D_max = max of the same,
+ * over the closed triangles of the two meshes after their rigid poses, with
+ * the Euclidean norm.  Penetrating meshes have D_min = 0 (Sec. 7).
+ *
+ * How: each mesh gets a perfect binary AABB tree whose leaves hold 1 or 2
+ * triangles (the paper's f12-BVH, Sec. 6.3), built on the GPU from Morton
+ * codes.  A query refits one tree into the other's frame, then expands the
+ * BVH-vs-BVH pair tree in rounds whose depth adapts to the front size
+ * (Alg. 1, Alg. 2, Sec. 5 "Adaptive Expansion Depth"), culling node pairs
+ * with the conventional and enhanced AABB bounds of Sec. 4 against a running
+ * best bound kept with integer atomics (Sec. 6.1, 6.4).  Leaf pairs go through
+ * an exact FP32 triangle-triangle distance; every candidate within the FP32
+ * error window of the best is re-evaluated in FP64 on the GPU.
+ *
+ * Conventions
+ *   - Every call returns gdist_status_t; GDIST_OK = 0.  Nothing throws across
+ *     the ABI.  gdist_last_error() returns a thread-local message describing
+ *     the most recent failure of the calling thread.
+ *   - Vertices are float32 triples (x,y,z), triangles uint32 triples of
+ *     0-based vertex indices, both row-major and densely packed.
+ *   - Poses are FP64 rigid transforms, world = R x + t, R row-major.
+ *   - Triangle indices in results are the caller's original 0-based indices.
+ *   - Points in results are in the world frame, FP64.
+ *   - A context is bound to one device and is not thread-safe: calls on one
+ *     context must not overlap.  Distinct contexts may be used concurrently.
+ */
+#ifndef GDIST_H
+#define GDIST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gdist_ctx* gdist_ctx_t;
+typedef uint64_t gdist_mesh_t; /* opaque handle; 0 is never a valid handle */
+
+typedef enum { GDIST_MIN = 0, GDIST_MAX = 1 } gdist_mode_t;
+
+typedef enum {
+  GDIST_OK = 0,
+  GDIST_E_INVALID = 1,  /* bad argument: sizes, indices, non-finite data, pose, mode */
+  GDIST_E_HANDLE = 2,   /* unknown or released mesh handle, or null context       */
+  GDIST_E_OOM = 3,      /* device or host allocation failed, or over the budget    */
+  GDIST_E_CAPACITY = 4, /* traversal front / candidate storage exhausted after the
+                           automatic retries with larger capacity                  */
+  GDIST_E_DEVICE = 5,   /* a HIP runtime call failed or a kernel reported an error */
+  GDIST_E_BUSY = 6      /* the context is in use by a running server               */
+} gdist_status_t;
+
+/* gdist_build flags */
+#define GDIST_BUILD_DEVICE_PTR 1u /* verts / tris are device pointers (e.g. torch
+                                     tensors on the context's device)            */
+
+/* gdist_result_t.flags */
+#define GDIST_F_TIED 1u  /* more than one triangle pair lies within the tie
+                            tolerance of the optimum; the reported pair is the
+                            lexicographically smallest (tri_a, tri_b) of them   */
+#define GDIST_F_ZERO 2u  /* min mode: the meshes touch or penetrate (distance 0) */
+
+typedef struct {
+  double R[9]; /* row-major rotation, orthonormal with det +1 */
+  double t[3];
+} gdist_pose_t;
+
+typedef struct {
+  double distance;      /* FP64 D_min or D_max, re-evaluated from the caller's FP32
+                           vertices and FP64 poses                                 */
+  double distance_fp32; /* the FP32 narrow-phase optimum (before FP64 re-eval)     */
+  double err_bound;     /* bound on |distance - exact real-arithmetic optimum of the
+                           FP32 input vertices under the FP64 poses|              */
+  double point_a[3];    /* world-frame point on tri_a of mesh a                   */
+  double point_b[3];    /* world-frame point on tri_b of mesh b (|pa-pb| is the
+                           pair's own FP64 distance, within the tie tolerance of
+                           `distance`)                                            */
+  uint32_t tri_a, tri_b;/* caller's triangle indices of the reported pair         */
+  uint32_t status;      /* gdist_status_t of this query (batched calls)           */
+  uint32_t flags;       /* GDIST_F_*                                              */
+  uint32_t n_candidates;/* triangle pairs re-evaluated in FP64                     */
+  uint32_t n_ties;      /* pairs within the tie tolerance of the optimum           */
+} gdist_result_t;
+
+typedef struct {
+  gdist_mesh_t a, b;    /* may be the same handle                                  */
+  gdist_pose_t pa, pb;  /* world poses of a and b                                  */
+  uint32_t mode;        /* gdist_mode_t                                            */
+  uint32_t reserved;    /* must be 0                                               */
+} gdist_query_desc_t;
+
+typedef struct {
+  uint32_t n_tris;      /* triangles                                               */
+  uint32_t n_leaves;    /* 2^floor(log2 n_tris)                                    */
+  uint32_t depth;       /* log2 n_leaves                                           */
+  uint32_t reserved;
+  uint64_t device_bytes;/* device memory held by the handle                        */
+  float root_box[6];    /* local-frame root box: min xyz, max xyz                 */
+} gdist_mesh_info_t;
+
+/* Counters of the most recent gdist_query / gdist_query_batch call on a
+ * context, summed over its queries.  Byte counts are algorithmic (what the
+ * method must move), not hardware counters. */
+typedef struct {
+  uint64_t rounds;          /* expansion rounds (grid-wide steps)                  */
+  uint64_t entries_popped;  /* front entries expanded                              */
+  uint64_t child_pairs;     /* node pairs whose bounds were evaluated              */
+  uint64_t entries_pushed;  /* node pairs appended to the next front              */
+  uint64_t leaf_pairs;      /* leaf pairs sent to the narrow phase                 */
+  uint64_t tri_pairs;       /* FP32 triangle-triangle evaluations                   */
+  uint64_t candidates;      /* candidates appended for FP64 re-evaluation          */
+  uint64_t front_peak;      /* largest front (entries)                             */
+  uint64_t bytes_refit;     /* refit: triangles read + boxes written               */
+  uint64_t bytes_traversal; /* entries read + child boxes read + entries written   */
+  uint64_t bytes_narrow;    /* leaf pairs read + triangles read + candidates       */
+  uint64_t retries;         /* capacity retries                                    */
+  double ms_refit;          /* device time of the refit kernels (HIP events)       */
+  double ms_traversal;      /* device time of the traversal + re-eval kernel       */
+  double ms_total;          /* device time of the whole query (refit to result)    */
+} gdist_stats_t;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  Allocates the context's stream and
+ * a small control block.  *out receives the context. */
+gdist_status_t gdist_create(int device, gdist_ctx_t* out);
+
+/* Destroy a context and every mesh and workspace it owns.  NULL is accepted. */
+gdist_status_t gdist_destroy(gdist_ctx_t ctx);
+
+/* Set a tunable.  Keys (value ranges are checked, E_INVALID otherwise):
+ *   "front_capacity"  entries per front buffer (16 B each), initial value
+ *   "leaf_capacity"   leaf pairs per narrow-phase buffer (16 B each)
+ *   "cand_capacity"   FP64 candidates (24 B each)
+ *   "max_retries"     capacity doublings before GDIST_E_CAPACITY
+ *   "expand_budget"   C of the adaptive depth rule (largest k with 4^k n < C)
+ *   "k_cap"           largest expansion depth per side and round (1..8)
+ *   "kappa"           FP32 inflation: delta = kappa * 2^-24 * M
+ *   "blocks_per_cu"   persistent-kernel workgroups per compute unit
+ *   "bounds"          0 = enhanced upper bounds (paper Sec. 4), 1 = conventional
+ *                     bounds only (the paper's ablation)
+ *   "memory_budget"   device bytes the context may hold (0 = unlimited)
+ */
+gdist_status_t gdist_set_option(gdist_ctx_t ctx, const char* key, double value);
+
+/* ------------------------------------------------------------------ meshes */
+
+/* Build the f12 tree of a mesh on the device (Morton keys, radix sort, leaf
+ * emit, level reduction; Sec. 6.3).  The caller's arrays are copied; the
+ * handle owns its device data until gdist_release.  Zero-area triangles are
+ * accepted.  E_INVALID: n_tris == 0 or >= 2^31, n_verts == 0, an index >=
+ * n_verts, or a non-finite vertex coordinate.  Synchronous. */
+gdist_status_t gdist_build(gdist_ctx_t ctx, const float* verts, uint32_t n_verts,
+                           const uint32_t* tris, uint32_t n_tris, uint32_t flags,
+                           gdist_mesh_t* out);
+
+/* Release a mesh handle and its device memory. */
+gdist_status_t gdist_release(gdist_ctx_t ctx, gdist_mesh_t mesh);
+
+gdist_status_t gdist_mesh_info(gdist_ctx_t ctx, gdist_mesh_t mesh, gdist_mesh_info_t* out);
+
+/* Copy a mesh's device tree to host memory (any pointer may be NULL):
+ *   boxes  float[2 * n_leaves][6]: node boxes in heap order (node 1 = root,
+ *          node n_leaves + j = leaf j; entry 0 unused), local frame;
+ *   tris   float[n_tris][9]: triangle vertices in leaf order;
+ *   orig   uint32[n_tris]: caller's index of each leaf-order triangle. */
+gdist_status_t gdist_mesh_export(gdist_ctx_t ctx, gdist_mesh_t mesh, float* boxes,
+                                 float* tris, uint32_t* orig);
+
+/* ----------------------------------------------------------------- queries */
+
+/* One query, one launch sequence, synchronous.  E_INVALID for a pose that is
+ * not a proper rotation (|R^T R - I|_inf > 1e-6 or det R < 0), a non-finite
+ * pose, or an unknown mode.  E_HANDLE for an unknown handle. */
+gdist_status_t gdist_query(gdist_ctx_t ctx, gdist_mesh_t a, gdist_mesh_t b,
+                           const gdist_pose_t* pa, const gdist_pose_t* pb,
+                           gdist_mode_t mode, gdist_result_t* out);
+
+/* n queries in one persistent launch (one refit launch set, one traversal
+ * launch, one re-evaluation).  Each query's result equals what gdist_query
+ * returns for it alone.  out[i].status carries the per-query status; the call
+ * returns the first non-OK status, or OK.  Synchronous. */
+gdist_status_t gdist_query_batch(gdist_ctx_t ctx, uint32_t n, const gdist_query_desc_t* q,
+                                 gdist_result_t* out);
+
+/* Counters of the most recent query call on this context. */
+gdist_status_t gdist_last_stats(gdist_ctx_t ctx, gdist_stats_t* out);
+
+/* Message for the most recent failure on the calling thread ("" if none). */
+const char* gdist_last_error(void);
+
+/* ------------------------------------------------------ device self-checks */
+
+/* Evaluate the device box-bound routine on n box pairs (host arrays).
+ * a, b: float[n][6]; out: float[n][4] = conventional lower bound of the min,
+ * enhanced upper bound of the min, conventional upper bound of the max,
+ * enhanced lower bound of the max (Sec. 4).  Exposed for testing. */
+gdist_status_t gdist_eval_box_bounds(gdist_ctx_t ctx, uint32_t n, const float* a,
+                                     const float* b, float* out);
+
+/* Evaluate the device triangle-triangle routines on n pairs (host arrays).
+ * p, q: float[n][9]; mode 0 = min, 1 = max.  out32: FP32 routine; out64: FP64
+ * routine on the same inputs widened to double.  Exposed for testing. */
+gdist_status_t gdist_eval_tri_tri(gdist_ctx_t ctx, uint32_t n, const float* p, const float* q,
+                                  uint32_t mode, float* out32, double* out64);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GDIST_H */

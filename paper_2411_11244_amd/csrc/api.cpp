@@ -1,0 +1,638 @@
+// Host side of libgdist: contexts, mesh handles, per-query workspaces and the
+// C ABI declared in include/gdist.h.  Every device step of a query runs in the
+// kernels of this library; the host validates, prepares the per-query
+// descriptors (FP64 relative pose rounded to FP32, tie tolerance), launches,
+// and copies the results back.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace gd;
+
+namespace {
+
+thread_local std::string t_err;
+
+gdist_status_t fail(gdist_status_t s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  t_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t _e = (expr);                                                                       \
+    if (_e != hipSuccess) return fail(GDIST_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Mesh {
+  uint32_t n_tris = 0, L = 0, depth = 0;
+  float* tris = nullptr;
+  uint32_t* orig = nullptr;
+  float* boxes = nullptr;
+  float root[6] = {0, 0, 0, 0, 0, 0};
+  uint64_t bytes = 0;
+};
+
+}  // namespace
+
+struct gdist_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::unordered_map<uint64_t, Mesh*> meshes;
+  uint64_t next_handle = 1;
+  // tunables
+  uint32_t front_cap = 1u << 22, leaf_cap = 1u << 22, cand_cap = 1u << 20;
+  uint32_t max_retries = 8, expand_budget = 1u << 18, k_cap = 5, blocks_per_cu = 0, bounds = 0;
+  double kappa = 64.0;
+  uint64_t memory_budget = 0, bytes_held = 0;
+  // workspace
+  DevBuf ws_boxes, front[2], leaf[2], cand, cand64, ctl, desc, st, res;
+  uint32_t trav_blocks = 0, trav_threads = 0;
+  gdist_stats_t last{};
+};
+
+namespace {
+
+gdist_status_t dalloc(gdist_ctx* c, size_t bytes, void** p) {
+  if (bytes == 0) bytes = 256;
+  if (c->memory_budget && c->bytes_held + bytes > c->memory_budget)
+    return fail(GDIST_E_OOM, "device memory budget exceeded (%llu + %zu > %llu bytes)",
+                (unsigned long long)c->bytes_held, bytes, (unsigned long long)c->memory_budget);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(GDIST_E_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  c->bytes_held += bytes;
+  return GDIST_OK;
+}
+
+void dfree(gdist_ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  c->bytes_held -= bytes ? bytes : 256;
+}
+
+gdist_status_t ensure(gdist_ctx* c, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return GDIST_OK;
+  if (b.p) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    dfree(c, b.p, b.bytes);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  gdist_status_t s = dalloc(c, bytes, &b.p);
+  if (s != GDIST_OK) return s;
+  b.bytes = bytes;
+  return GDIST_OK;
+}
+
+void release_buf(gdist_ctx* c, DevBuf& b) {
+  dfree(c, b.p, b.bytes);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+gdist_status_t check_pose(const gdist_pose_t* p, const char* which) {
+  if (!p) return fail(GDIST_E_INVALID, "pose %s is NULL", which);
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(p->R[i])) return fail(GDIST_E_INVALID, "pose %s has a non-finite rotation entry", which);
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(p->t[i])) return fail(GDIST_E_INVALID, "pose %s has a non-finite translation", which);
+  double err = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += p->R[3 * k + i] * p->R[3 * k + j];
+      err = std::fmax(err, std::fabs(s - (i == j ? 1.0 : 0.0)));
+    }
+  const double* R = p->R;
+  double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+               R[2] * (R[3] * R[7] - R[4] * R[6]);
+  if (err > 1e-6 || det < 0.0)
+    return fail(GDIST_E_INVALID, "pose %s is not a proper rotation (|R^T R - I| = %.3g, det = %.6f)", which, err, det);
+  return GDIST_OK;
+}
+
+// largest |world coordinate| over the 8 corners of a local box under a pose
+double world_extent(const float* box, const gdist_pose_t& P) {
+  double m = 0.0;
+  for (int c = 0; c < 8; ++c) {
+    double x = (c & 1) ? box[3] : box[0], y = (c & 2) ? box[4] : box[1], z = (c & 4) ? box[5] : box[2];
+    for (int r = 0; r < 3; ++r) {
+      double w = P.R[3 * r] * x + P.R[3 * r + 1] * y + P.R[3 * r + 2] * z + P.t[r];
+      m = std::fmax(m, std::fabs(w));
+    }
+  }
+  return m;
+}
+
+Mesh* find_mesh(gdist_ctx* c, gdist_mesh_t h) {
+  auto it = c->meshes.find(h);
+  return it == c->meshes.end() ? nullptr : it->second;
+}
+
+uint32_t floor_log2(uint32_t x) { return 31u - (uint32_t)__builtin_clz(x); }
+
+gdist_status_t refresh_grid(gdist_ctx* c) {
+  HIPCHK(traverse_grid(c->device, c->blocks_per_cu, &c->trav_blocks, &c->trav_threads));
+  return GDIST_OK;
+}
+
+// enough workgroups for the candidate lists seen in practice; the kernels are
+// grid-stride, so any count is correct
+uint32_t reeval_blocks(uint32_t n_slots) { return n_slots > 64 ? 1024u : 256u; }
+
+struct SlotPlan {
+  Mesh* A;
+  Mesh* B;
+  size_t box_off;  // float offset of B's refitted boxes in ws_boxes
+};
+
+gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out) {
+  if (n == 0) return GDIST_OK;
+  if (!q || !out) return fail(GDIST_E_INVALID, "NULL query or result array");
+  std::vector<SlotDesc> desc(n);
+  std::vector<SlotPlan> plan(n);
+  size_t box_floats = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    Mesh* ma = find_mesh(c, q[i].a);
+    Mesh* mb = find_mesh(c, q[i].b);
+    if (!ma || !mb) return fail(GDIST_E_HANDLE, "query %u: unknown mesh handle", i);
+    if (q[i].mode > 1) return fail(GDIST_E_INVALID, "query %u: unknown mode %u", i, q[i].mode);
+    gdist_status_t s = check_pose(&q[i].pa, "a");
+    if (s != GDIST_OK) return s;
+    s = check_pose(&q[i].pb, "b");
+    if (s != GDIST_OK) return s;
+    // refit the smaller tree into the larger one's frame
+    bool swapped = ma->n_tris < mb->n_tris;
+    Mesh* A = swapped ? mb : ma;
+    Mesh* B = swapped ? ma : mb;
+    const gdist_pose_t& PA = swapped ? q[i].pb : q[i].pa;
+    const gdist_pose_t& PB = swapped ? q[i].pa : q[i].pb;
+    SlotDesc& d = desc[i];
+    std::memset(&d, 0, sizeof(d));
+    d.boxA = A->boxes;
+    d.trisA = A->tris;
+    d.trisB = B->tris;
+    d.origA = A->orig;
+    d.origB = B->orig;
+    d.nA = A->n_tris;
+    d.nB = B->n_tris;
+    d.LA = A->L;
+    d.LB = B->L;
+    d.depthA = A->depth;
+    d.depthB = B->depth;
+    d.mode = q[i].mode;
+    d.enhanced = c->bounds == 0 ? 1u : 0u;
+    d.swapped = swapped ? 1u : 0u;
+    d.kappa_u = (float)(c->kappa * std::ldexp(1.0, -24));
+    // B local -> A local: R = RA^T RB, t = RA^T (tB - tA)
+    for (int r = 0; r < 3; ++r) {
+      for (int col = 0; col < 3; ++col) {
+        double s2 = 0.0;
+        for (int k = 0; k < 3; ++k) s2 += PA.R[3 * k + r] * PB.R[3 * k + col];
+        d.T.R[3 * r + col] = (float)s2;
+      }
+      double s3 = 0.0;
+      for (int k = 0; k < 3; ++k) s3 += PA.R[3 * k + r] * (PB.t[k] - PA.t[k]);
+      d.T.t[r] = (float)s3;
+    }
+    for (int k = 0; k < 9; ++k) {
+      d.RA[k] = PA.R[k];
+      d.RB[k] = PB.R[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+      d.tA[k] = PA.t[k];
+      d.tB[k] = PB.t[k];
+    }
+    double M = std::fmax(world_extent(A->root, PA), world_extent(B->root, PB));
+    d.tau = 1e-12 * std::fmax(1.0, M);
+    d.err_bound = 1e-13 * std::fmax(1.0, M);
+    plan[i].A = A;
+    plan[i].B = B;
+    plan[i].box_off = box_floats;
+    box_floats += 6ull * 2ull * B->L;
+    box_floats = (box_floats + 63) & ~(size_t)63;
+  }
+  gdist_status_t s = ensure(c, c->ws_boxes, box_floats * sizeof(float));
+  if (s != GDIST_OK) return s;
+  for (uint32_t i = 0; i < n; ++i) desc[i].boxB = (const float*)c->ws_boxes.p + plan[i].box_off;
+  if ((s = ensure(c, c->desc, sizeof(SlotDesc) * n)) != GDIST_OK) return s;
+  if ((s = ensure(c, c->st, sizeof(SlotState) * n)) != GDIST_OK) return s;
+  if ((s = ensure(c, c->res, sizeof(gdist_result_t) * n)) != GDIST_OK) return s;
+  if ((s = ensure(c, c->ctl, sizeof(Ctl))) != GDIST_OK) return s;
+  HIPCHK(hipMemcpyAsync(c->desc.p, desc.data(), sizeof(SlotDesc) * n, hipMemcpyHostToDevice, c->stream));
+
+  std::memset(&c->last, 0, sizeof(c->last));
+  HIPCHK(hipEventRecord(c->ev[0], c->stream));
+  for (uint32_t i = 0; i < n; ++i) {
+    const Mesh* B = plan[i].B;
+    HIPCHK(launch_refit(B->tris, B->n_tris, B->L, desc[i].T, (float*)c->ws_boxes.p + plan[i].box_off, c->stream));
+    c->last.bytes_refit += 36ull * B->n_tris + 24ull * (2ull * B->L - 1ull);
+  }
+  HIPCHK(hipEventRecord(c->ev[1], c->stream));
+
+  uint32_t fcap = c->front_cap < n ? n : c->front_cap;
+  uint32_t lcap = c->leaf_cap < n ? n : c->leaf_cap;
+  uint32_t ccap = c->cand_cap;
+  Ctl hctl;
+  for (uint32_t attempt = 0;; ++attempt) {
+    for (int b = 0; b < 2; ++b) {
+      if ((s = ensure(c, c->front[b], 16ull * fcap)) != GDIST_OK) return s;
+      if ((s = ensure(c, c->leaf[b], 16ull * lcap)) != GDIST_OK) return s;
+    }
+    if ((s = ensure(c, c->cand, sizeof(Cand) * (size_t)ccap)) != GDIST_OK) return s;
+    if ((s = ensure(c, c->cand64, sizeof(double) * (size_t)ccap)) != GDIST_OK) return s;
+    TravParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.desc = (const SlotDesc*)c->desc.p;
+    p.st = (SlotState*)c->st.p;
+    p.res = (gdist_result_t*)c->res.p;
+    p.front[0] = (uint4*)c->front[0].p;
+    p.front[1] = (uint4*)c->front[1].p;
+    p.leaf[0] = (uint4*)c->leaf[0].p;
+    p.leaf[1] = (uint4*)c->leaf[1].p;
+    p.cand = (Cand*)c->cand.p;
+    p.cand_d64 = (double*)c->cand64.p;
+    p.ctl = (Ctl*)c->ctl.p;
+    p.front_cap = fcap;
+    p.leaf_cap = lcap;
+    p.cand_cap = ccap;
+    p.n_slots = n;
+    p.expand_budget = c->expand_budget;
+    p.k_cap = c->k_cap;
+    p.spin_limit = 1u << 26;
+    HIPCHK(launch_init(p, c->stream));
+    if (attempt == 0) HIPCHK(hipEventRecord(c->ev[2], c->stream));
+    HIPCHK(launch_traverse(p, c->trav_blocks, c->trav_threads, c->stream));
+    HIPCHK(launch_reeval(p, reeval_blocks(n), c->stream));
+    HIPCHK(hipEventRecord(c->ev[3], c->stream));
+    HIPCHK(hipMemcpyAsync(&hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(out, c->res.p, sizeof(gdist_result_t) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (hctl.abort) return fail(GDIST_E_DEVICE, "traversal grid barrier timed out");
+    if (!hctl.overflow) break;
+    if (attempt >= c->max_retries)
+      return fail(GDIST_E_CAPACITY, "traversal storage exhausted (front %u, leaf %u, candidates %u entries)", fcap,
+                  lcap, ccap);
+    c->last.retries++;
+    auto grow = [](uint32_t v) { return v >= (1u << 30) ? v : v * 2u; };
+    if (hctl.overflow & 1u) fcap = grow(fcap);
+    if (hctl.overflow & 2u) lcap = grow(lcap);
+    if (hctl.overflow & 4u) ccap = grow(ccap);
+  }
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+  c->last.ms_refit = ms;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev[2], c->ev[3]));
+  c->last.ms_traversal = ms;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
+  c->last.ms_total = ms;
+  c->last.rounds = hctl.stats[ST_ROUNDS];
+  c->last.entries_popped = hctl.stats[ST_POPPED];
+  c->last.child_pairs = hctl.stats[ST_CHILD];
+  c->last.entries_pushed = hctl.stats[ST_PUSHED];
+  c->last.leaf_pairs = hctl.stats[ST_LEAF];
+  c->last.tri_pairs = hctl.stats[ST_TRI];
+  c->last.candidates = hctl.stats[ST_CAND];
+  c->last.front_peak = hctl.stats[ST_PEAK];
+  c->last.bytes_traversal = 16ull * c->last.entries_popped + 48ull * c->last.child_pairs + 16ull * c->last.entries_pushed;
+  c->last.bytes_narrow = 16ull * c->last.leaf_pairs + 72ull * c->last.tri_pairs + 16ull * c->last.candidates;
+  gdist_status_t first = GDIST_OK;
+  for (uint32_t i = 0; i < n; ++i)
+    if (out[i].status != GDIST_OK && first == GDIST_OK) first = (gdist_status_t)out[i].status;
+  if (first != GDIST_OK) return fail(first, "a query found no admissible candidate");
+  return GDIST_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gdist_last_error(void) { return t_err.c_str(); }
+
+gdist_status_t gdist_create(int device, gdist_ctx_t* out) {
+  if (!out) return fail(GDIST_E_INVALID, "NULL output pointer");
+  *out = nullptr;
+  int count = 0;
+  HIPCHK(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(GDIST_E_INVALID, "device %d out of range (%d devices)", device, count);
+  HIPCHK(hipSetDevice(device));
+  gdist_ctx* c = new gdist_ctx();
+  c->device = device;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(GDIST_E_DEVICE, "hipStreamCreate failed");
+  }
+  for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&c->ev[i]));
+  gdist_status_t s = refresh_grid(c);
+  if (s != GDIST_OK) {
+    gdist_destroy(c);
+    return s;
+  }
+  *out = c;
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_destroy(gdist_ctx_t c) {
+  if (!c) return GDIST_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->meshes) {
+    Mesh* m = kv.second;
+    dfree(c, m->tris, 36ull * m->n_tris);
+    dfree(c, m->orig, 4ull * m->n_tris);
+    dfree(c, m->boxes, 48ull * m->L);
+    delete m;
+  }
+  c->meshes.clear();
+  DevBuf* bufs[] = {&c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->cand,
+                    &c->cand64, &c->ctl, &c->desc, &c->st, &c->res};
+  for (DevBuf* b : bufs) release_buf(c, *b);
+  for (int i = 0; i < 4; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_set_option(gdist_ctx_t c, const char* key, double v) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (!key) return fail(GDIST_E_INVALID, "NULL key");
+  auto u32opt = [&](uint32_t* dst, double lo, double hi) -> gdist_status_t {
+    if (!(v >= lo && v <= hi) || v != std::floor(v))
+      return fail(GDIST_E_INVALID, "option %s=%g out of range [%g, %g]", key, v, lo, hi);
+    *dst = (uint32_t)v;
+    return GDIST_OK;
+  };
+  std::string k(key);
+  if (k == "front_capacity") return u32opt(&c->front_cap, 64, 1u << 30);
+  if (k == "leaf_capacity") return u32opt(&c->leaf_cap, 64, 1u << 30);
+  if (k == "cand_capacity") return u32opt(&c->cand_cap, 64, 1u << 30);
+  if (k == "max_retries") return u32opt(&c->max_retries, 0, 32);
+  if (k == "expand_budget") return u32opt(&c->expand_budget, 4, 1u << 30);
+  if (k == "k_cap") return u32opt(&c->k_cap, 1, 8);
+  if (k == "bounds") return u32opt(&c->bounds, 0, 1);
+  if (k == "blocks_per_cu") {
+    gdist_status_t s = u32opt(&c->blocks_per_cu, 0, 64);
+    if (s != GDIST_OK) return s;
+    HIPCHK(hipSetDevice(c->device));
+    return refresh_grid(c);
+  }
+  if (k == "kappa") {
+    if (!(v >= 1.0 && v <= 1e6)) return fail(GDIST_E_INVALID, "option kappa=%g out of range [1, 1e6]", v);
+    c->kappa = v;
+    return GDIST_OK;
+  }
+  if (k == "memory_budget") {
+    if (!(v >= 0.0)) return fail(GDIST_E_INVALID, "option memory_budget=%g must be >= 0", v);
+    c->memory_budget = (uint64_t)v;
+    return GDIST_OK;
+  }
+  return fail(GDIST_E_INVALID, "unknown option '%s'", key);
+}
+
+gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const uint32_t* tris, uint32_t nt,
+                           uint32_t flags, gdist_mesh_t* out) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (!out) return fail(GDIST_E_INVALID, "NULL output handle pointer");
+  *out = 0;
+  if (!verts || !tris) return fail(GDIST_E_INVALID, "NULL vertex or triangle array");
+  if (nt == 0 || nt >= (1u << 31)) return fail(GDIST_E_INVALID, "n_tris = %u out of range [1, 2^31)", nt);
+  if (nv == 0) return fail(GDIST_E_INVALID, "n_verts = 0");
+  if (flags & ~GDIST_BUILD_DEVICE_PTR) return fail(GDIST_E_INVALID, "unknown build flags 0x%x", flags);
+  HIPCHK(hipSetDevice(c->device));
+  const bool dev = (flags & GDIST_BUILD_DEVICE_PTR) != 0;
+  gdist_status_t s = GDIST_OK;
+  // temporaries
+  void *dv = nullptr, *df = nullptr, *keys = nullptr, *keys2 = nullptr, *vals = nullptr, *vals2 = nullptr,
+       *hist = nullptr, *misc = nullptr;
+  const size_t vb = 12ull * nv, fb = 12ull * nt, hb = 4ull * radix_hist_words(nt);
+  Mesh* m = new Mesh();
+  m->n_tris = nt;
+  m->L = 1u << floor_log2(nt);
+  m->depth = floor_log2(m->L);
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(c->stream);
+    if (!dev) {
+      dfree(c, dv, vb);
+      dfree(c, df, fb);
+    }
+    dfree(c, keys, 8ull * nt);
+    dfree(c, keys2, 8ull * nt);
+    dfree(c, vals, 4ull * nt);
+    dfree(c, vals2, 4ull * nt);
+    dfree(c, hist, hb);
+    dfree(c, misc, 64);
+  };
+  auto abort_build = [&](gdist_status_t st) {
+    std::string msg = t_err;
+    cleanup();
+    dfree(c, m->tris, 36ull * nt);
+    dfree(c, m->orig, 4ull * nt);
+    dfree(c, m->boxes, 48ull * m->L);
+    delete m;
+    t_err = msg;
+    return st;
+  };
+#define TRY(expr)                         \
+  do {                                    \
+    gdist_status_t _s = (expr);           \
+    if (_s != GDIST_OK) return abort_build(_s); \
+  } while (0)
+#define TRYHIP(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return abort_build(fail(GDIST_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e))); \
+  } while (0)
+  if (dev) {
+    dv = (void*)verts;
+    df = (void*)tris;
+  } else {
+    TRY(dalloc(c, vb, &dv));
+    TRY(dalloc(c, fb, &df));
+    TRYHIP(hipMemcpyAsync(dv, verts, vb, hipMemcpyHostToDevice, c->stream));
+    TRYHIP(hipMemcpyAsync(df, tris, fb, hipMemcpyHostToDevice, c->stream));
+  }
+  TRY(dalloc(c, 64, &misc));
+  int* cbox = (int*)misc;
+  uint32_t* vflags = (uint32_t*)((char*)misc + 32);
+  TRYHIP(launch_validate_centroids((const float*)dv, nv, (const uint32_t*)df, nt, cbox, vflags, c->stream));
+  uint32_t hflags = 0;
+  TRYHIP(hipMemcpyAsync(&hflags, vflags, 4, hipMemcpyDeviceToHost, c->stream));
+  TRYHIP(hipStreamSynchronize(c->stream));
+  if (hflags & 1u) return abort_build(fail(GDIST_E_INVALID, "a triangle index is >= n_verts (%u)", nv));
+  if (hflags & 2u) return abort_build(fail(GDIST_E_INVALID, "a vertex coordinate is not finite"));
+  TRY(dalloc(c, 8ull * nt, &keys));
+  TRY(dalloc(c, 8ull * nt, &keys2));
+  TRY(dalloc(c, 4ull * nt, &vals));
+  TRY(dalloc(c, 4ull * nt, &vals2));
+  TRY(dalloc(c, hb, &hist));
+  TRY(dalloc(c, 36ull * nt, (void**)&m->tris));
+  TRY(dalloc(c, 4ull * nt, (void**)&m->orig));
+  TRY(dalloc(c, 48ull * m->L, (void**)&m->boxes));
+  TRYHIP(launch_morton((const float*)dv, (const uint32_t*)df, nt, cbox, (uint64_t*)keys, (uint32_t*)vals, c->stream));
+  int in_tmp = 0;
+  TRYHIP(launch_radix_sort((uint64_t*)keys, (uint32_t*)vals, (uint64_t*)keys2, (uint32_t*)vals2, nt,
+                           (uint32_t*)hist, c->stream, &in_tmp));
+  const uint32_t* sorted = (const uint32_t*)(in_tmp ? vals2 : vals);
+  TRYHIP(launch_emit((const float*)dv, (const uint32_t*)df, nt, sorted, m->tris, m->orig, c->stream));
+  Xf32 I;
+  std::memset(&I, 0, sizeof(I));
+  I.R[0] = I.R[4] = I.R[8] = 1.f;
+  TRYHIP(launch_refit(m->tris, nt, m->L, I, m->boxes, c->stream));
+  TRYHIP(hipMemcpyAsync(m->root, m->boxes + 6, 24, hipMemcpyDeviceToHost, c->stream));
+  TRYHIP(hipStreamSynchronize(c->stream));
+#undef TRY
+#undef TRYHIP
+  cleanup();
+  m->bytes = 36ull * nt + 4ull * nt + 48ull * m->L;
+  uint64_t h = c->next_handle++;
+  c->meshes[h] = m;
+  *out = h;
+  (void)s;
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_release(gdist_ctx_t c, gdist_mesh_t h) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  Mesh* m = find_mesh(c, h);
+  if (!m) return fail(GDIST_E_HANDLE, "unknown mesh handle %llu", (unsigned long long)h);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  dfree(c, m->tris, 36ull * m->n_tris);
+  dfree(c, m->orig, 4ull * m->n_tris);
+  dfree(c, m->boxes, 48ull * m->L);
+  c->meshes.erase(h);
+  delete m;
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_mesh_info(gdist_ctx_t c, gdist_mesh_t h, gdist_mesh_info_t* out) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (!out) return fail(GDIST_E_INVALID, "NULL output");
+  Mesh* m = find_mesh(c, h);
+  if (!m) return fail(GDIST_E_HANDLE, "unknown mesh handle %llu", (unsigned long long)h);
+  std::memset(out, 0, sizeof(*out));
+  out->n_tris = m->n_tris;
+  out->n_leaves = m->L;
+  out->depth = m->depth;
+  out->device_bytes = m->bytes;
+  for (int i = 0; i < 6; ++i) out->root_box[i] = m->root[i];
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_mesh_export(gdist_ctx_t c, gdist_mesh_t h, float* boxes, float* tris, uint32_t* orig) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  Mesh* m = find_mesh(c, h);
+  if (!m) return fail(GDIST_E_HANDLE, "unknown mesh handle %llu", (unsigned long long)h);
+  HIPCHK(hipSetDevice(c->device));
+  if (boxes) HIPCHK(hipMemcpy(boxes, m->boxes, 48ull * m->L, hipMemcpyDeviceToHost));
+  if (tris) HIPCHK(hipMemcpy(tris, m->tris, 36ull * m->n_tris, hipMemcpyDeviceToHost));
+  if (orig) HIPCHK(hipMemcpy(orig, m->orig, 4ull * m->n_tris, hipMemcpyDeviceToHost));
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_query(gdist_ctx_t c, gdist_mesh_t a, gdist_mesh_t b, const gdist_pose_t* pa,
+                           const gdist_pose_t* pb, gdist_mode_t mode, gdist_result_t* out) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (!out) return fail(GDIST_E_INVALID, "NULL result pointer");
+  if (!pa || !pb) return fail(GDIST_E_INVALID, "NULL pose");
+  gdist_query_desc_t d;
+  std::memset(&d, 0, sizeof(d));
+  d.a = a;
+  d.b = b;
+  d.pa = *pa;
+  d.pb = *pb;
+  d.mode = (uint32_t)mode;
+  HIPCHK(hipSetDevice(c->device));
+  return run_queries(c, 1, &d, out);
+}
+
+gdist_status_t gdist_query_batch(gdist_ctx_t c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  HIPCHK(hipSetDevice(c->device));
+  return run_queries(c, n, q, out);
+}
+
+gdist_status_t gdist_last_stats(gdist_ctx_t c, gdist_stats_t* out) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (!out) return fail(GDIST_E_INVALID, "NULL output");
+  *out = c->last;
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_eval_box_bounds(gdist_ctx_t c, uint32_t n, const float* a, const float* b, float* out) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (n == 0) return GDIST_OK;
+  if (!a || !b || !out) return fail(GDIST_E_INVALID, "NULL array");
+  HIPCHK(hipSetDevice(c->device));
+  void *da = nullptr, *db = nullptr, *dout = nullptr;
+  gdist_status_t s;
+  if ((s = dalloc(c, 24ull * n, &da)) != GDIST_OK) return s;
+  if ((s = dalloc(c, 24ull * n, &db)) != GDIST_OK) { dfree(c, da, 24ull * n); return s; }
+  if ((s = dalloc(c, 16ull * n, &dout)) != GDIST_OK) { dfree(c, da, 24ull * n); dfree(c, db, 24ull * n); return s; }
+  hipError_t e = hipMemcpy(da, a, 24ull * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(db, b, 24ull * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_eval_bounds(n, (const float*)da, (const float*)db, (float*)dout, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 16ull * n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dfree(c, da, 24ull * n);
+  dfree(c, db, 24ull * n);
+  dfree(c, dout, 16ull * n);
+  if (e != hipSuccess) return fail(GDIST_E_DEVICE, "box-bound evaluation failed: %s", hipGetErrorString(e));
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_eval_tri_tri(gdist_ctx_t c, uint32_t n, const float* p, const float* q, uint32_t mode,
+                                  float* out32, double* out64) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (n == 0) return GDIST_OK;
+  if (!p || !q || !out32 || !out64) return fail(GDIST_E_INVALID, "NULL array");
+  if (mode > 1) return fail(GDIST_E_INVALID, "unknown mode %u", mode);
+  HIPCHK(hipSetDevice(c->device));
+  void *dp = nullptr, *dq = nullptr, *d32 = nullptr, *d64 = nullptr;
+  gdist_status_t s;
+  if ((s = dalloc(c, 36ull * n, &dp)) != GDIST_OK) return s;
+  if ((s = dalloc(c, 36ull * n, &dq)) != GDIST_OK) { dfree(c, dp, 36ull * n); return s; }
+  if ((s = dalloc(c, 4ull * n, &d32)) != GDIST_OK) { dfree(c, dp, 36ull * n); dfree(c, dq, 36ull * n); return s; }
+  if ((s = dalloc(c, 8ull * n, &d64)) != GDIST_OK) {
+    dfree(c, dp, 36ull * n); dfree(c, dq, 36ull * n); dfree(c, d32, 4ull * n);
+    return s;
+  }
+  hipError_t e = hipMemcpy(dp, p, 36ull * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dq, q, 36ull * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = launch_eval_tri_tri(n, (const float*)dp, (const float*)dq, mode, (float*)d32, (double*)d64, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out32, d32, 4ull * n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out64, d64, 8ull * n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dfree(c, dp, 36ull * n);
+  dfree(c, dq, 36ull * n);
+  dfree(c, d32, 4ull * n);
+  dfree(c, d64, 8ull * n);
+  if (e != hipSuccess) return fail(GDIST_E_DEVICE, "triangle evaluation failed: %s", hipGetErrorString(e));
+  return GDIST_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+// GPU construction of the f12 tree (gDist Sec. 6.3): triangles are ordered by
+// the Morton code of their centroid, then split evenly over 2^floor(log2 N)
+// leaves (1 or 2 consecutive triangles each) of a perfect binary tree stored
+// implicitly in heap order.  The node boxes are produced by the refit kernels
+// with the identity transform.
+//
+// Kernels here: input validation + centroid bounds, Morton keys (63 bits,
+// 21 per axis), a stable LSD radix sort of (u64 key, u32 value) pairs with
+// 8-bit digits, and the scatter of triangles into leaf order.
+#include "internal.hpp"
+
+namespace gd {
+
+// Order-preserving map of a float onto a signed int (for atomic min/max).
+__device__ __forceinline__ int ordered(float f) {
+  int i = __float_as_int(f);
+  return i >= 0 ? i : (i ^ 0x7fffffff);
+}
+__host__ __device__ inline float unordered(int i) {
+  int j = i >= 0 ? i : (i ^ 0x7fffffff);
+  float f;
+  __builtin_memcpy(&f, &j, 4);
+  return f;
+}
+
+// flags: bit 0 = index out of range, bit 1 = non-finite vertex.
+// cbox: 6 ints (ordered floats): centroid min xyz, centroid max xyz.
+__global__ void k_validate_centroids(const float* __restrict__ v, uint32_t nv, const uint32_t* __restrict__ f,
+                                     uint32_t nt, int* __restrict__ cbox, uint32_t* __restrict__ flags) {
+  float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
+  float hi[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
+  uint32_t bad = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    float x = v[3 * i], y = v[3 * i + 1], z = v[3 * i + 2];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) bad |= 2u;
+  }
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
+    uint32_t i0 = f[3 * t], i1 = f[3 * t + 1], i2 = f[3 * t + 2];
+    if (i0 >= nv || i1 >= nv || i2 >= nv) {
+      bad |= 1u;
+      continue;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float c = (v[3ull * i0 + k] + v[3ull * i1 + k] + v[3ull * i2 + k]) * (1.0f / 3.0f);
+      lo[k] = fminf(lo[k], c);
+      hi[k] = fmaxf(hi[k], c);
+    }
+  }
+  __shared__ float s_lo[3][256], s_hi[3][256];
+  __shared__ uint32_t s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  if (bad) atomicOr(&s_bad, bad);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    s_lo[k][threadIdx.x] = lo[k];
+    s_hi[k][threadIdx.x] = hi[k];
+  }
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        s_lo[k][threadIdx.x] = fminf(s_lo[k][threadIdx.x], s_lo[k][threadIdx.x + s]);
+        s_hi[k][threadIdx.x] = fmaxf(s_hi[k][threadIdx.x], s_hi[k][threadIdx.x + s]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      atomicMin(&cbox[k], ordered(s_lo[k][0]));
+      atomicMax(&cbox[3 + k], ordered(s_hi[k][0]));
+    }
+    if (s_bad) atomicOr(flags, s_bad);
+  }
+}
+
+__global__ void k_init_cbox(int* cbox, uint32_t* flags) {
+  if (threadIdx.x < 3) {
+    cbox[threadIdx.x] = ordered(__builtin_huge_valf());
+    cbox[3 + threadIdx.x] = ordered(-__builtin_huge_valf());
+  }
+  if (threadIdx.x == 0) *flags = 0;
+}
+
+// Spread the low 21 bits of x so that bit i lands at bit 3i.
+__device__ __forceinline__ uint64_t spread3(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | (x << 32)) & 0x001f00000000ffffull;
+  x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__global__ void k_morton(const float* __restrict__ v, const uint32_t* __restrict__ f, uint32_t nt,
+                         const int* __restrict__ cbox, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  uint64_t code = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float lo = unordered(cbox[k]), hi = unordered(cbox[3 + k]);
+    uint32_t i0 = f[3 * t], i1 = f[3 * t + 1], i2 = f[3 * t + 2];
+    float c = (v[3ull * i0 + k] + v[3ull * i1 + k] + v[3ull * i2 + k]) * (1.0f / 3.0f);
+    float ext = hi - lo;
+    float u = ext > 0.f ? (c - lo) / ext : 0.f;
+    float s = u * 2097152.0f;  // 2^21 cells per axis
+    uint32_t q = s <= 0.f ? 0u : (s >= 2097151.0f ? 2097151u : (uint32_t)s);
+    code |= spread3(q) << (2 - k);   // x on the highest of each bit triple
+  }
+  keys[t] = code;
+  vals[t] = (uint32_t)t;
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int kRsThreads = 256;
+constexpr int kRsRowsPerWave = 16;
+constexpr int kRsTile = kRsThreads * kRsRowsPerWave;  // 4096 keys per block
+
+// hist[d * nblocks + b] = number of keys of block b with digit d
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t n,
+                                                         uint32_t shift, uint32_t* __restrict__ hist,
+                                                         uint32_t nblocks) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsRowsPerWave; ++r) {
+    uint64_t i = base + (uint64_t)r * kRsThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// In-place exclusive scan of `len` counts by one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ a, uint64_t len) {
+  __shared__ uint32_t s[1024];
+  uint64_t chunk = (len + 1023) / 1024;
+  uint64_t b = threadIdx.x * chunk, e = b + chunk < len ? b + chunk : len;
+  uint32_t sum = 0;
+  for (uint64_t i = b; i < e; ++i) sum += a[i];
+  s[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t x = threadIdx.x >= (uint32_t)off ? s[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = s[threadIdx.x] - sum;  // exclusive prefix of this chunk
+  for (uint64_t i = b; i < e; ++i) {
+    uint32_t x = a[i];
+    a[i] = run;
+    run += x;
+  }
+}
+
+// Stable scatter.  Wave w of the block ranks rows w*16 .. w*16+15 of the
+// block's tile (a row = 64 consecutive keys) in order: lanes holding the same
+// digit are found with eight ballots, their order inside the row comes from
+// mbcnt, and a per-wave running count per digit carries the order across
+// rows.  A final per-digit prefix over the four waves makes the block-local
+// rank, added to the digit's global offset for this block.
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                            const uint32_t* __restrict__ vin,
+                                                            uint64_t* __restrict__ kout,
+                                                            uint32_t* __restrict__ vout, uint32_t n,
+                                                            uint32_t shift, const uint32_t* __restrict__ offs,
+                                                            uint32_t nblocks) {
+  __shared__ uint32_t wc[kRsThreads / kWave][257];
+  const uint32_t w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  for (uint32_t i = threadIdx.x; i < (kRsThreads / kWave) * 257; i += kRsThreads) (&wc[0][0])[i] = 0;
+  __syncthreads();
+  uint64_t key[kRsRowsPerWave];
+  uint32_t val[kRsRowsPerWave], dig[kRsRowsPerWave], rk[kRsRowsPerWave];
+  const uint64_t base = (uint64_t)blockIdx.x * kRsTile + (uint64_t)w * kRsRowsPerWave * kWave;
+  const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int r = 0; r < kRsRowsPerWave; ++r) {
+    uint64_t i = base + (uint64_t)r * kWave + lane;
+    bool ok = i < n;
+    key[r] = ok ? kin[i] : 0ull;
+    val[r] = ok ? vin[i] : 0u;
+    uint32_t d = ok ? (uint32_t)((key[r] >> shift) & 255u) : 256u;
+    dig[r] = d;
+    uint64_t same = __ballot(ok);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      uint64_t m = __ballot((d >> bit) & 1u);
+      same &= ((d >> bit) & 1u) ? m : ~m;
+    }
+    uint32_t prev = ok ? wc[w][d] : 0u;
+    rk[r] = prev + (uint32_t)__popcll(same & lt);
+    // lowest lane of each digit group advances that digit's running count
+    if (ok && (same & lt) == 0ull) wc[w][d] = prev + (uint32_t)__popcll(same);
+  }
+  __syncthreads();
+  {
+    uint32_t d = threadIdx.x;  // 256 threads, one per digit
+    uint32_t run = 0;
+#pragma unroll
+    for (int q = 0; q < kRsThreads / kWave; ++q) {
+      uint32_t c = wc[q][d];
+      wc[q][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRsRowsPerWave; ++r) {
+    if (dig[r] < 256u) {
+      uint32_t pos = offs[(uint64_t)dig[r] * nblocks + blockIdx.x] + wc[w][dig[r]] + rk[r];
+      kout[pos] = key[r];
+      vout[pos] = val[r];
+    }
+  }
+}
+
+// Triangles in sorted (= leaf) order, plus the caller index of each.
+__global__ void k_emit(const float* __restrict__ v, const uint32_t* __restrict__ f, uint32_t nt,
+                       const uint32_t* __restrict__ sorted, float* __restrict__ tris, uint32_t* __restrict__ orig) {
+  uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nt) return;
+  uint32_t o = sorted[s];
+  orig[s] = o;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    uint32_t vi = f[3ull * o + c];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) tris[9 * s + 3 * c + k] = v[3ull * vi + k];
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_validate_centroids(const float* v, uint32_t nv, const uint32_t* f, uint32_t nt, int* cbox,
+                                     uint32_t* flags, hipStream_t s) {
+  k_init_cbox<<<1, 64, 0, s>>>(cbox, flags);
+  uint64_t work = nv > nt ? nv : nt;
+  uint32_t blocks = (uint32_t)((work + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  if (blocks == 0) blocks = 1;
+  k_validate_centroids<<<blocks, 256, 0, s>>>(v, nv, f, nt, cbox, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_morton(const float* v, const uint32_t* f, uint32_t nt, const int* cbox, uint64_t* keys,
+                         uint32_t* vals, hipStream_t s) {
+  k_morton<<<(nt + 255) / 256, 256, 0, s>>>(v, f, nt, cbox, keys, vals);
+  return hipGetLastError();
+}
+
+size_t radix_hist_words(uint32_t n) { return (size_t)256 * ((n + kRsTile - 1) / kRsTile); }
+
+hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
+                             uint32_t n, uint32_t* hist, hipStream_t s, int* result_in_tmp) {
+  uint32_t nblocks = (n + kRsTile - 1) / kRsTile;
+  uint64_t *ki = keys, *ko = keys_tmp;
+  uint32_t *vi = vals, *vo = vals_tmp;
+  for (uint32_t shift = 0; shift < 64; shift += 8) {
+    k_rs_hist<<<nblocks, kRsThreads, 0, s>>>(ki, n, shift, hist, nblocks);
+    k_rs_scan<<<1, 1024, 0, s>>>(hist, (uint64_t)256 * nblocks);
+    k_rs_scatter<<<nblocks, kRsThreads, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblocks);
+    uint64_t* tk = ki; ki = ko; ko = tk;
+    uint32_t* tv = vi; vi = vo; vo = tv;
+  }
+  *result_in_tmp = (ki == keys_tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_emit(const float* v, const uint32_t* f, uint32_t nt, const uint32_t* sorted, float* tris,
+                       uint32_t* orig, hipStream_t s) {
+  k_emit<<<(nt + 255) / 256, 256, 0, s>>>(v, f, nt, sorted, tris, orig);
+  return hipGetLastError();
+}
+
+}  // namespace gd

@@ -1,0 +1,114 @@
+// Internal declarations shared by the host library and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gdist.h"
+#include "gdist_dev.hpp"
+
+namespace gd {
+
+// Per-query description, written by the host once per query.
+// "A" is the tree kept static (its local frame is the query frame); "B" is
+// the tree refitted into A's frame.  `swapped` says the caller's mesh a is B.
+struct SlotDesc {
+  const float* boxA;    // [2 LA][6], A local frame
+  const float* boxB;    // [2 LB][6], refitted into A's frame
+  const float* trisA;   // [nA][9] leaf order, A local frame
+  const float* trisB;   // [nB][9] leaf order, B local frame
+  const uint32_t* origA;
+  const uint32_t* origB;
+  uint32_t nA, nB, LA, LB;
+  uint32_t depthA, depthB;
+  uint32_t mode;        // 0 = min, 1 = max
+  uint32_t enhanced;    // 1 = enhanced bounds (Sec. 4), 0 = conventional only
+  uint32_t swapped;
+  float kappa_u;        // delta = kappa_u * M
+  Xf32 T;               // B local -> A local, FP32
+  double RA[9], tA[3];  // world pose of A, FP64
+  double RB[9], tB[3];  // world pose of B, FP64
+  double tau;           // tie tolerance (FP64)
+  double err_bound;
+};
+
+// Per-query mutable state on the device.
+struct SlotState {
+  uint32_t best;             // float bits: min mode = upper bound of D_min (+delta),
+                             // max mode = lower bound of D_max (-delta)
+  uint32_t best32;           // float bits of the FP32 narrow-phase optimum
+  float delta;               // FP32 error window
+  uint32_t n_ties;
+  unsigned long long key_d;  // double bits of the FP64 optimum
+  unsigned long long key_pair;  // (caller tri a << 32) | caller tri b of the reported pair
+  uint32_t n_admitted;       // candidates that passed the final window
+  uint32_t pad;
+};
+
+// Candidate triangle pair for FP64 re-evaluation (positions in leaf order).
+struct Cand {
+  float d32;
+  uint32_t slot;
+  uint32_t ia, ib;
+};
+
+enum StatIdx {
+  ST_POPPED = 0, ST_CHILD = 1, ST_PUSHED = 2, ST_LEAF = 3, ST_TRI = 4, ST_CAND = 5, ST_PEAK = 6, ST_ROUNDS = 7,
+  ST_N = 8
+};
+
+// Control block of one persistent traversal launch.
+struct Ctl {
+  uint32_t front_len[3];
+  uint32_t leaf_len[3];
+  uint32_t cand_len;
+  uint32_t overflow;       // bit 0 front, bit 1 leaf pairs, bit 2 candidates
+  uint32_t abort;          // a grid barrier timed out
+  uint32_t bar_count;
+  uint32_t bar_gen;
+  uint32_t pad;
+  unsigned long long stats[ST_N];
+};
+
+struct TravParams {
+  const SlotDesc* desc;
+  SlotState* st;
+  gdist_result_t* res;
+  uint4* front[2];
+  uint4* leaf[2];
+  Cand* cand;
+  double* cand_d64;
+  Ctl* ctl;
+  uint32_t front_cap, leaf_cap, cand_cap;
+  uint32_t n_slots;
+  uint32_t expand_budget;
+  uint32_t k_cap;
+  uint32_t spin_limit;
+  uint32_t pad;
+};
+
+// build.hip
+hipError_t launch_validate_centroids(const float* v, uint32_t nv, const uint32_t* f, uint32_t nt, int* cbox,
+                                     uint32_t* flags, hipStream_t s);
+hipError_t launch_morton(const float* v, const uint32_t* f, uint32_t nt, const int* cbox, uint64_t* keys,
+                         uint32_t* vals, hipStream_t s);
+size_t radix_hist_words(uint32_t n);
+hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, uint32_t n,
+                             uint32_t* hist, hipStream_t s, int* result_in_tmp);
+hipError_t launch_emit(const float* v, const uint32_t* f, uint32_t nt, const uint32_t* sorted, float* tris,
+                       uint32_t* orig, hipStream_t s);
+
+// refit.hip
+hipError_t launch_refit(const float* tris, uint32_t n, uint32_t L, const Xf32& T, float* boxes, hipStream_t s);
+
+// traverse.hip
+hipError_t launch_init(const TravParams& p, hipStream_t s);
+hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, uint32_t* threads);
+hipError_t launch_traverse(const TravParams& p, uint32_t blocks, uint32_t threads, hipStream_t s);
+hipError_t launch_reeval(const TravParams& p, uint32_t blocks, hipStream_t s);
+
+// selfcheck.hip
+hipError_t launch_eval_bounds(uint32_t n, const float* a, const float* b, float* out, hipStream_t s);
+hipError_t launch_eval_tri_tri(uint32_t n, const float* p, const float* q, uint32_t mode, float* o32, double* o64,
+                               hipStream_t s);
+
+}  // namespace gd

@@ -19,3 +19,12 @@ def orc():
     oracle.build_oracle(force=False)
     oracle._load()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gctx():
+    """One libgdist context on device 0 for the whole GPU session."""
+    from paper_2411_11244_amd import gdist
+    ctx = gdist.gdist_create(0)
+    yield ctx
+    gdist.gdist_destroy(ctx)
