@@ -112,7 +112,8 @@ typedef struct {
   uint64_t child_pairs;     /* node pairs whose bounds were evaluated              */
   uint64_t entries_pushed;  /* node pairs appended to the next front              */
   uint64_t leaf_pairs;      /* leaf pairs sent to the narrow phase                 */
-  uint64_t tri_pairs;       /* FP32 triangle-triangle evaluations                   */
+  uint64_t tri_pairs;       /* triangle pairs given the separating-axis test      */
+  uint64_t tri_full;        /* exact FP32 triangle-triangle evaluations            */
   uint64_t candidates;      /* candidates appended for FP64 re-evaluation          */
   uint64_t front_peak;      /* largest front (entries)                             */
   uint64_t bytes_refit;     /* refit: triangles read + boxes written               */

@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <unordered_map>
@@ -58,13 +60,17 @@ struct gdist_ctx {
   std::unordered_map<uint64_t, Mesh*> meshes;
   uint64_t next_handle = 1;
   // tunables
-  uint32_t front_cap = 1u << 22, leaf_cap = 1u << 22, cand_cap = 1u << 20;
+  uint32_t front_cap = 1u << 24, leaf_cap = 1u << 24, cand_cap = 1u << 21;
   uint32_t max_retries = 8, expand_budget = 1u << 18, k_cap = 5, blocks_per_cu = 0, bounds = 0;
   double kappa = 64.0;
   uint64_t memory_budget = 0, bytes_held = 0;
   // workspace
-  DevBuf ws_boxes, front[2], leaf[2], cand, cand64, ctl, desc, st, res;
+  DevBuf ws_boxes, front[2], leaf[2], counts, cand, cand64, ctl, desc, st, res;
   uint32_t trav_blocks = 0, trav_threads = 0;
+  int wall_khz = 0;
+  bool trace = false;
+  uint32_t group_hint = 0;                 // largest group of queries that fit one launch
+  unsigned long long last_ctl_sum[ST_N] = {};
   gdist_stats_t last{};
 };
 
@@ -161,6 +167,111 @@ gdist_status_t refresh_grid(gdist_ctx* c) {
 // grid-stride, so any count is correct
 uint32_t reeval_blocks(uint32_t n_slots) { return n_slots > 64 ? 1024u : 256u; }
 
+constexpr uint32_t kCapLimit = 1u << 28;      // entries per front / leaf buffer
+constexpr uint32_t kCandLimit = 1u << 26;     // FP64 candidates
+
+void print_trace(gdist_ctx* c, uint32_t g0, uint32_t gn, const Ctl& h);
+
+// Traversal + FP64 re-evaluation of slots [g0, g0 + gn), whose descriptors are
+// already on the device.  On storage overflow the capacities grow and the
+// group is run again; when they cannot grow any more and gn > 1, returns
+// E_CAPACITY with *split set.
+gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_result_t* out, bool* first_launch,
+                              bool* split) {
+  gdist_status_t s;
+  const uint32_t nb = c->trav_blocks;
+  // per-workgroup segments; the root pairs all start in segment 0
+  auto seg_of = [&](uint32_t cap) {
+    uint32_t v = cap / nb;
+    if (v < gn) v = gn;
+    return v < 1u ? 1u : v;
+  };
+  uint32_t sf = seg_of(c->front_cap), sl = seg_of(c->leaf_cap);
+  uint32_t ccap = c->cand_cap;
+  Ctl hctl;
+  if ((s = ensure(c, c->counts, 16ull * nb)) != GDIST_OK) return s;
+  for (uint32_t attempt = 0;; ++attempt) {
+    const uint64_t fcap = (uint64_t)sf * nb, lcap = (uint64_t)sl * nb;
+    for (int b = 0; b < 2; ++b) {
+      if ((s = ensure(c, c->front[b], 16ull * fcap)) != GDIST_OK) return s;
+      if ((s = ensure(c, c->leaf[b], 16ull * lcap)) != GDIST_OK) return s;
+    }
+    if ((s = ensure(c, c->cand, sizeof(Cand) * (size_t)ccap)) != GDIST_OK) return s;
+    if ((s = ensure(c, c->cand64, sizeof(double) * (size_t)ccap)) != GDIST_OK) return s;
+    TravParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.desc = (const SlotDesc*)c->desc.p + g0;
+    p.st = (SlotState*)c->st.p + g0;
+    p.res = (gdist_result_t*)c->res.p + g0;
+    p.front[0] = (uint4*)c->front[0].p;
+    p.front[1] = (uint4*)c->front[1].p;
+    p.leaf[0] = (uint4*)c->leaf[0].p;
+    p.leaf[1] = (uint4*)c->leaf[1].p;
+    uint32_t* cnt = (uint32_t*)c->counts.p;
+    p.fcount[0] = cnt;
+    p.fcount[1] = cnt + nb;
+    p.lcount[0] = cnt + 2 * nb;
+    p.lcount[1] = cnt + 3 * nb;
+    p.nblocks = nb;
+    p.cand = (Cand*)c->cand.p;
+    p.cand_d64 = (double*)c->cand64.p;
+    p.ctl = (Ctl*)c->ctl.p;
+    p.seg_front = sf;
+    p.seg_leaf = sl;
+    p.cand_cap = ccap;
+    p.n_slots = gn;
+    p.expand_budget = c->expand_budget;
+    p.k_cap = c->k_cap;
+    p.spin_limit = 1u << 26;
+    HIPCHK(launch_init(p, c->stream));
+    if (*first_launch) HIPCHK(hipEventRecord(c->ev[2], c->stream));
+    *first_launch = false;
+    HIPCHK(launch_traverse(p, c->trav_blocks, c->trav_threads, c->stream));
+    HIPCHK(launch_reeval(p, reeval_blocks(gn), c->stream));
+    HIPCHK(hipEventRecord(c->ev[3], c->stream));
+    HIPCHK(hipMemcpyAsync(&hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(out, p.res, sizeof(gdist_result_t) * gn, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (hctl.abort) return fail(GDIST_E_DEVICE, "traversal grid barrier timed out");
+    if (!hctl.overflow) {
+      // keep grown capacities for the next queries on this context
+      if (fcap > c->front_cap) c->front_cap = (uint32_t)fcap;
+      if (lcap > c->leaf_cap) c->leaf_cap = (uint32_t)lcap;
+      if (ccap > c->cand_cap) c->cand_cap = ccap;
+      break;
+    }
+    const bool can_grow = ((hctl.overflow & 1u) == 0 || 2ull * fcap <= kCapLimit) &&
+                          ((hctl.overflow & 2u) == 0 || 2ull * lcap <= kCapLimit) &&
+                          ((hctl.overflow & 4u) == 0 || ccap < kCandLimit);
+    if (!can_grow || attempt >= c->max_retries) {
+      *split = gn > 1;
+      return fail(GDIST_E_CAPACITY, "traversal storage exhausted (front %llu, leaf %llu, candidates %u entries, %u queries)",
+                  (unsigned long long)fcap, (unsigned long long)lcap, ccap, gn);
+    }
+    c->last.retries++;
+    if (hctl.overflow & 1u) sf *= 2u;
+    if (hctl.overflow & 2u) sl *= 2u;
+    if (hctl.overflow & 4u) ccap = ccap >= kCandLimit / 2 ? kCandLimit : ccap * 2u;
+  }
+  for (int i = 0; i < ST_N; ++i) {
+    if (i == ST_PEAK) c->last_ctl_sum[i] = std::max(c->last_ctl_sum[i], hctl.stats[i]);
+    else c->last_ctl_sum[i] += hctl.stats[i];
+  }
+  if (c->trace) print_trace(c, g0, gn, hctl);
+  return GDIST_OK;
+}
+
+void print_trace(gdist_ctx* c, uint32_t g0, uint32_t gn, const Ctl& h) {
+  uint32_t R = (uint32_t)h.stats[ST_ROUNDS];
+  double khz = c->wall_khz > 0 ? (double)c->wall_khz : 1e5;
+  fprintf(stderr, "[gdist] slots %u..%u, %u rounds\n", g0, g0 + gn - 1, R);
+  for (uint32_t r = 0; r < R && r < kTraceRounds; ++r) {
+    unsigned long long t1 = (r + 1 < R && r + 1 < kTraceRounds) ? h.trace_t[r + 1] : h.trace_end;
+    fprintf(stderr, "[gdist]   round %2u  front %10u  leaf pairs %10u  %9.1f us\n", r, h.trace_n[r], h.trace_nl[r],
+            (double)(t1 - h.trace_t[r]) * 1e3 / khz);
+  }
+}
+
 struct SlotPlan {
   Mesh* A;
   Mesh* B;
@@ -251,54 +362,24 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
   }
   HIPCHK(hipEventRecord(c->ev[1], c->stream));
 
-  uint32_t fcap = c->front_cap < n ? n : c->front_cap;
-  uint32_t lcap = c->leaf_cap < n ? n : c->leaf_cap;
-  uint32_t ccap = c->cand_cap;
-  Ctl hctl;
-  for (uint32_t attempt = 0;; ++attempt) {
-    for (int b = 0; b < 2; ++b) {
-      if ((s = ensure(c, c->front[b], 16ull * fcap)) != GDIST_OK) return s;
-      if ((s = ensure(c, c->leaf[b], 16ull * lcap)) != GDIST_OK) return s;
+  // Traversal in groups of slots.  A group whose storage overflows first
+  // grows its capacities (up to kCapLimit entries per buffer); a group that
+  // still does not fit is split in half, and later calls on this context
+  // start from the smaller group size.
+  std::memset(&c->last_ctl_sum, 0, sizeof(c->last_ctl_sum));
+  uint32_t group = (c->group_hint && c->group_hint < n) ? c->group_hint : n;
+  bool first_launch = true;
+  for (uint32_t g0 = 0; g0 < n;) {
+    const uint32_t gn = group < n - g0 ? group : n - g0;
+    bool split = false;
+    s = traverse_group(c, g0, gn, out + g0, &first_launch, &split);
+    if (s == GDIST_E_CAPACITY && split) {
+      group = gn / 2 > 0 ? gn / 2 : 1;
+      c->group_hint = group;
+      continue;
     }
-    if ((s = ensure(c, c->cand, sizeof(Cand) * (size_t)ccap)) != GDIST_OK) return s;
-    if ((s = ensure(c, c->cand64, sizeof(double) * (size_t)ccap)) != GDIST_OK) return s;
-    TravParams p;
-    std::memset(&p, 0, sizeof(p));
-    p.desc = (const SlotDesc*)c->desc.p;
-    p.st = (SlotState*)c->st.p;
-    p.res = (gdist_result_t*)c->res.p;
-    p.front[0] = (uint4*)c->front[0].p;
-    p.front[1] = (uint4*)c->front[1].p;
-    p.leaf[0] = (uint4*)c->leaf[0].p;
-    p.leaf[1] = (uint4*)c->leaf[1].p;
-    p.cand = (Cand*)c->cand.p;
-    p.cand_d64 = (double*)c->cand64.p;
-    p.ctl = (Ctl*)c->ctl.p;
-    p.front_cap = fcap;
-    p.leaf_cap = lcap;
-    p.cand_cap = ccap;
-    p.n_slots = n;
-    p.expand_budget = c->expand_budget;
-    p.k_cap = c->k_cap;
-    p.spin_limit = 1u << 26;
-    HIPCHK(launch_init(p, c->stream));
-    if (attempt == 0) HIPCHK(hipEventRecord(c->ev[2], c->stream));
-    HIPCHK(launch_traverse(p, c->trav_blocks, c->trav_threads, c->stream));
-    HIPCHK(launch_reeval(p, reeval_blocks(n), c->stream));
-    HIPCHK(hipEventRecord(c->ev[3], c->stream));
-    HIPCHK(hipMemcpyAsync(&hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(out, c->res.p, sizeof(gdist_result_t) * n, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (hctl.abort) return fail(GDIST_E_DEVICE, "traversal grid barrier timed out");
-    if (!hctl.overflow) break;
-    if (attempt >= c->max_retries)
-      return fail(GDIST_E_CAPACITY, "traversal storage exhausted (front %u, leaf %u, candidates %u entries)", fcap,
-                  lcap, ccap);
-    c->last.retries++;
-    auto grow = [](uint32_t v) { return v >= (1u << 30) ? v : v * 2u; };
-    if (hctl.overflow & 1u) fcap = grow(fcap);
-    if (hctl.overflow & 2u) lcap = grow(lcap);
-    if (hctl.overflow & 4u) ccap = grow(ccap);
+    if (s != GDIST_OK) return s;
+    g0 += gn;
   }
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
@@ -307,14 +388,16 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
   c->last.ms_traversal = ms;
   HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[3]));
   c->last.ms_total = ms;
-  c->last.rounds = hctl.stats[ST_ROUNDS];
-  c->last.entries_popped = hctl.stats[ST_POPPED];
-  c->last.child_pairs = hctl.stats[ST_CHILD];
-  c->last.entries_pushed = hctl.stats[ST_PUSHED];
-  c->last.leaf_pairs = hctl.stats[ST_LEAF];
-  c->last.tri_pairs = hctl.stats[ST_TRI];
-  c->last.candidates = hctl.stats[ST_CAND];
-  c->last.front_peak = hctl.stats[ST_PEAK];
+  const unsigned long long* st = c->last_ctl_sum;
+  c->last.rounds = st[ST_ROUNDS];
+  c->last.entries_popped = st[ST_POPPED];
+  c->last.child_pairs = st[ST_CHILD];
+  c->last.entries_pushed = st[ST_PUSHED];
+  c->last.leaf_pairs = st[ST_LEAF];
+  c->last.tri_pairs = st[ST_TRI];
+  c->last.tri_full = st[ST_FULL];
+  c->last.candidates = st[ST_CAND];
+  c->last.front_peak = st[ST_PEAK];
   c->last.bytes_traversal = 16ull * c->last.entries_popped + 48ull * c->last.child_pairs + 16ull * c->last.entries_pushed;
   c->last.bytes_narrow = 16ull * c->last.leaf_pairs + 72ull * c->last.tri_pairs + 16ull * c->last.candidates;
   gdist_status_t first = GDIST_OK;
@@ -344,6 +427,9 @@ gdist_status_t gdist_create(int device, gdist_ctx_t* out) {
     return fail(GDIST_E_DEVICE, "hipStreamCreate failed");
   }
   for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&c->ev[i]));
+  (void)hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, device);
+  const char* tr = getenv("GDIST_TRACE");
+  c->trace = tr && tr[0] && tr[0] != '0';
   gdist_status_t s = refresh_grid(c);
   if (s != GDIST_OK) {
     gdist_destroy(c);
@@ -365,7 +451,7 @@ gdist_status_t gdist_destroy(gdist_ctx_t c) {
     delete m;
   }
   c->meshes.clear();
-  DevBuf* bufs[] = {&c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->cand,
+  DevBuf* bufs[] = {&c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->counts, &c->cand,
                     &c->cand64, &c->ctl, &c->desc, &c->st, &c->res};
   for (DevBuf* b : bufs) release_buf(c, *b);
   for (int i = 0; i < 4; ++i)

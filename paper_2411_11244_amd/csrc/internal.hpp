@@ -53,13 +53,13 @@ struct Cand {
 
 enum StatIdx {
   ST_POPPED = 0, ST_CHILD = 1, ST_PUSHED = 2, ST_LEAF = 3, ST_TRI = 4, ST_CAND = 5, ST_PEAK = 6, ST_ROUNDS = 7,
-  ST_N = 8
+  ST_FULL = 8, ST_N = 9
 };
+
+constexpr uint32_t kTraceRounds = 48;
 
 // Control block of one persistent traversal launch.
 struct Ctl {
-  uint32_t front_len[3];
-  uint32_t leaf_len[3];
   uint32_t cand_len;
   uint32_t overflow;       // bit 0 front, bit 1 leaf pairs, bit 2 candidates
   uint32_t abort;          // a grid barrier timed out
@@ -67,18 +67,26 @@ struct Ctl {
   uint32_t bar_gen;
   uint32_t pad;
   unsigned long long stats[ST_N];
+  // per-round device timestamps (constant-rate wall clock) and front sizes
+  unsigned long long trace_t[kTraceRounds];
+  unsigned long long trace_end;
+  uint32_t trace_n[kTraceRounds];
+  uint32_t trace_nl[kTraceRounds];
 };
 
 struct TravParams {
   const SlotDesc* desc;
   SlotState* st;
   gdist_result_t* res;
-  uint4* front[2];
+  uint4* front[2];         // segmented: workgroup b owns [b * seg_front, (b+1) * seg_front)
   uint4* leaf[2];
+  uint32_t* fcount[2];     // per-workgroup entry counts of front[i] (nblocks each)
+  uint32_t* lcount[2];
   Cand* cand;
   double* cand_d64;
   Ctl* ctl;
-  uint32_t front_cap, leaf_cap, cand_cap;
+  uint32_t seg_front, seg_leaf, cand_cap;
+  uint32_t nblocks;        // workgroups of the traversal launch
   uint32_t n_slots;
   uint32_t expand_budget;
   uint32_t k_cap;

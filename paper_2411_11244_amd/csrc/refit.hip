@@ -23,8 +23,9 @@ __global__ __launch_bounds__(kRefitThreads) void k_refit_leaves(const float* __r
   Box b;
   if (j < S) {
     uint32_t leaf = blockIdx.x * S + j;
-    uint32_t start = (uint32_t)(((uint64_t)leaf * n) / L);
-    uint32_t end = (uint32_t)(((uint64_t)(leaf + 1) * n) / L);
+    const uint32_t D = 31u - (uint32_t)__clz(L);   // L = 2^D
+    uint32_t start = (uint32_t)(((uint64_t)leaf * n) >> D);
+    uint32_t end = (uint32_t)(((uint64_t)(leaf + 1) * n) >> D);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       b.lo[k] = __builtin_huge_valf();

@@ -4,10 +4,12 @@
 // front length that the paper reads back to the host every iteration is read
 // on the device, so the host does not synchronise inside a query.
 //
+// Before the rounds, one wave per query descends greedily from the root pair
+// (always into the child pair with the best bound) to one leaf pair and
+// evaluates its triangles: the running best starts close to the optimum, so
+// the breadth-first rounds cull with a tight bound from the first level on.
+//
 // Round r (all workgroups, grid-stride over 64-item waves):
-//   * narrow phase on the leaf pairs emitted in round r-1: one lane per
-//     triangle pair (leaves hold 1 or 2 triangles, so 4 lanes per leaf pair);
-//     exact FP32 distance, running best improved, candidates appended;
 //   * expansion of the front: with n entries, k = largest value with
 //     4^k n < C, clamped to [1, k_cap] (Sec. 5); lane t of the round handles
 //     entry t >> 2k and the descendant pair named by the low 2k bits of t
@@ -15,7 +17,13 @@
 //     reach their leaves (a side at its leaf level gives its budget to the
 //     other).  Children are culled against the running best with the
 //     conventional lower bound; the enhanced upper bound improves the best
-//     (Alg. 2, Sec. 6.1).
+//     (Alg. 2, Sec. 6.1).  Leaf-leaf survivors go to the narrow phase.
+//   * narrow phase on the leaf pairs emitted in round r-1, one lane per
+//     triangle pair (leaves hold 1 or 2 triangles, so 4 lanes per leaf pair).
+//     A cheap separating-axis lower bound (the two triangle planes and the
+//     centroid axis) rejects most pairs; the survivors are packed into a
+//     per-wave LDS queue and the exact triangle-triangle distance runs on
+//     full waves of 64 queued pairs.
 //   * survivors are appended with one atomic per wave (ballot + mbcnt
 //     compaction); the best is kept as float bits with integer atomics after
 //     a wave-level reduction (Sec. 6.4).
@@ -33,6 +41,9 @@
 namespace gd {
 
 constexpr int kTravThreads = 256;
+constexpr int kWavesPerBlock = kTravThreads / kWave;
+constexpr uint32_t kQueue = 320;  // per-wave LDS queue of triangle pairs (63 + 4 x 64)
+constexpr int kRows = 4;          // expansion rows per wave iteration
 
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -41,22 +52,29 @@ __device__ __forceinline__ void st_rlx(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide barrier for a cooperative launch.  Every thread releases its
-// writes at device scope before the workgroup barrier; one thread per
-// workgroup arrives and waits with a bounded spin (a timeout raises `abort`
-// so every wave still reaches the end of the kernel).
+// Grid-wide barrier for a cooperative launch.  The workgroup barrier orders
+// every wave's writes before thread 0's device-scope release; thread 0 then
+// arrives and waits with a bounded spin (a timeout raises `abort` so every
+// wave still reaches the end of the kernel) and acquires at device scope for
+// the whole workgroup before the closing workgroup barrier.
 __device__ void grid_sync(Ctl* c, uint32_t spin_limit) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  // every wave's stores have reached L2 (vmcnt counts stores on this target)
+  // before the workgroup barrier, so thread 0's L2 writeback covers them
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
     uint32_t gen = ld_rlx(&c->bar_gen);
     uint32_t arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == gridDim.x - 1) {
       st_rlx(&c->bar_count, 0u);
       __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
+      // relaxed polling: an acquire load here would invalidate L2 on every
+      // poll; the single acquire fence below orders the reads that follow
       uint32_t spins = 0;
-      while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (ld_rlx(&c->bar_gen) == gen) {
         __builtin_amdgcn_s_sleep(2);
         if (++spins > spin_limit) {
           st_rlx(&c->abort, 1u);
@@ -64,9 +82,9 @@ __device__ void grid_sync(Ctl* c, uint32_t spin_limit) {
         }
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 __device__ __forceinline__ uint32_t first_lane(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
@@ -122,158 +140,436 @@ __device__ __forceinline__ void add_stat(unsigned long long* s, int idx, bool pr
   if (lane == 0 && m) atomicAdd(&s[idx], (unsigned long long)__popcll(m));
 }
 
-__global__ void k_init(TravParams p) {
-  Ctl* c = p.ctl;
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < 3; ++i) {
-      c->front_len[i] = 0;
-      c->leaf_len[i] = 0;
-    }
-    c->cand_len = 0;
-    c->overflow = 0;
-    c->abort = 0;
-    c->bar_count = 0;
-    c->bar_gen = 0;
-    for (int i = 0; i < ST_N; ++i) c->stats[i] = 0;
-  }
-  __syncthreads();
-  for (uint32_t s = threadIdx.x; s < p.n_slots; s += blockDim.x) {
-    const SlotDesc& d = p.desc[s];
-    Box ra = load_box(d.boxA, 1), rb = load_box(d.boxB, 1);
-    float M = 0.f;
+__device__ __forceinline__ uint32_t level_of(uint32_t node) { return 31u - (uint32_t)__clz(node); }
+
+// Share 2k expansion levels between the two sides (Sec. 6.3 thread mapping):
+// each side takes at most k, a side that has fewer levels left gives the rest
+// to the other.
+__device__ __forceinline__ void split_levels(uint32_t remA, uint32_t remB, uint32_t kk, uint32_t& kA,
+                                             uint32_t& kB) {
+  uint32_t h = kk / 2;
+  kA = remA < h ? remA : h;
+  kB = remB < kk - kA ? remB : kk - kA;
+  kA = remA < kk - kB ? remA : kk - kB;
+}
+
+// Triangle range of leaf node `node` of a tree with n triangles and 2^D leaves.
+__device__ __forceinline__ void leaf_range(uint32_t node, uint32_t D, uint32_t n, uint32_t& s, uint32_t& e) {
+  uint32_t j = node - (1u << D);
+  s = (uint32_t)(((uint64_t)j * n) >> D);
+  e = (uint32_t)(((uint64_t)(j + 1) * n) >> D);
+}
+
+__device__ __forceinline__ void load_pair(const SlotDesc* d, uint32_t pa, uint32_t pb, V3<float>* P, V3<float>* Q) {
+  float a[9], b[9];
+  load_tri(d->trisA, pa, a);
+  load_tri_xf(d->trisB, pb, d->T, b);
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      M = fmaxf(M, fmaxf(fmaxf(fabsf(ra.lo[k]), fabsf(ra.hi[k])), fmaxf(fabsf(rb.lo[k]), fabsf(rb.hi[k]))));
-    M = fmaxf(M, 1e-30f);
-    float delta = d.kappa_u * M;
+  for (int v = 0; v < 3; ++v) {
+    P[v] = mk<float>(a[3 * v], a[3 * v + 1], a[3 * v + 2]);
+    Q[v] = mk<float>(b[3 * v], b[3 * v + 1], b[3 * v + 2]);
+  }
+}
+
+// Lower bound of the distance between triangles P and Q from three candidate
+// separating axes: the normal of P, the normal of Q, and the line through the
+// two centroids (a projection of both sets onto an axis never increases
+// distances).  Zero when no axis separates.
+__device__ __forceinline__ float sep_lower(const V3<float>* P, const V3<float>* Q) {
+  float lb = 0.f;
+  V3<float> n = cross(P[1] - P[0], P[2] - P[0]);
+  float nn = dot(n, n);
+  if (nn > 0.f) {
+    float s0 = dot(n, Q[0] - P[0]), s1 = dot(n, Q[1] - P[0]), s2 = dot(n, Q[2] - P[0]);
+    float s = fmaxf(fminf(s0, fminf(s1, s2)), -fmaxf(s0, fmaxf(s1, s2)));
+    lb = fmaxf(lb, s * rsqrtf(nn));
+  }
+  V3<float> m = cross(Q[1] - Q[0], Q[2] - Q[0]);
+  float mm = dot(m, m);
+  if (mm > 0.f) {
+    float s0 = dot(m, P[0] - Q[0]), s1 = dot(m, P[1] - Q[0]), s2 = dot(m, P[2] - Q[0]);
+    float s = fmaxf(fminf(s0, fminf(s1, s2)), -fmaxf(s0, fmaxf(s1, s2)));
+    lb = fmaxf(lb, s * rsqrtf(mm));
+  }
+  V3<float> u = (Q[0] + Q[1] + Q[2]) - (P[0] + P[1] + P[2]);
+  float uu = dot(u, u);
+  if (uu > 0.f) {
+    float pmax = fmaxf(dot(P[0], u), fmaxf(dot(P[1], u), dot(P[2], u)));
+    float qmin = fminf(dot(Q[0], u), fminf(dot(Q[1], u), dot(Q[2], u)));
+    lb = fmaxf(lb, (qmin - pmax) * rsqrtf(uu));
+  }
+  return lb;
+}
+
+// Zero the control block and the round-0 segment counts.
+__global__ void k_reset(TravParams p) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(p.ctl);
+  for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) w[i] = 0u;
+  for (uint32_t i = threadIdx.x; i < p.nblocks; i += blockDim.x) {
+    p.fcount[0][i] = 0u;
+    p.lcount[0][i] = 0u;
+  }
+}
+
+// One wave per query: error window, root bounds, greedy dive, root entry.
+__global__ __launch_bounds__(kTravThreads) void k_init(TravParams p) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t s = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (s >= p.n_slots) return;
+  const SlotDesc& d = p.desc[s];
+  const uint32_t mode = d.mode;
+  const bool enh = d.enhanced != 0;
+  Box ra = load_box(d.boxA, 1), rb = load_box(d.boxB, 1);
+  float M = 0.f;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    M = fmaxf(M, fmaxf(fmaxf(fabsf(ra.lo[k]), fabsf(ra.hi[k])), fmaxf(fabsf(rb.lo[k]), fabsf(rb.hi[k]))));
+  M = fmaxf(M, 1e-30f);
+  const float delta = d.kappa_u * M;
+  float key, best;
+  if (mode == 0) {
+    float lo, up;
+    bounds_min(ra, rb, enh, lo, up);
+    best = up + delta;
+    key = lo;
+  } else {
+    float up, lo;
+    bounds_max(ra, rb, enh, up, lo);
+    best = fmaxf(lo - delta, 0.f);
+    key = up;
+  }
+  // greedy descent: 64 child pairs (3 levels per side) per step
+  uint32_t a = 1u, b = 1u;
+  for (int step = 0; step < 64; ++step) {
+    uint32_t remA = d.depthA - level_of(a), remB = d.depthB - level_of(b);
+    if (remA == 0u && remB == 0u) break;
+    uint32_t kA, kB;
+    split_levels(remA, remB, 6u, kA, kB);
+    const bool act = lane < (1u << (kA + kB));
+    const uint32_t ca = (a << kA) | (lane & ((1u << kA) - 1u));
+    const uint32_t cb = (b << kB) | ((lane >> kA) & ((1u << kB) - 1u));
+    float sel = mode == 0 ? __builtin_huge_valf() : -__builtin_huge_valf();
+    float imp = mode == 0 ? __builtin_huge_valf() : 0.f;
+    if (act) {
+      Box ba = load_box(d.boxA, ca), bb = load_box(d.boxB, cb);
+      float x, y;
+      if (mode == 0) {
+        bounds_min(ba, bb, enh, x, y);
+        sel = x;
+        imp = y;
+      } else {
+        bounds_max(ba, bb, enh, x, y);
+        sel = x;
+        imp = y;
+      }
+    }
+    if (mode == 0) {
+      best = fminf(best, wave_min(imp) + delta);
+      float ext = wave_min(sel);
+      uint32_t L = first_lane(__ballot(act && sel == ext));
+      a = __shfl(ca, L, 64);
+      b = __shfl(cb, L, 64);
+    } else {
+      best = fmaxf(best, fmaxf(wave_max(imp) - delta, 0.f));
+      float ext = wave_max(sel);
+      uint32_t L = first_lane(__ballot(act && sel == ext));
+      a = __shfl(ca, L, 64);
+      b = __shfl(cb, L, 64);
+    }
+  }
+  {
+    uint32_t sa, ea, sb, eb;
+    leaf_range(a, d.depthA, d.nA, sa, ea);
+    leaf_range(b, d.depthB, d.nB, sb, eb);
+    const uint32_t pa = sa + (lane & 1u), pb = sb + ((lane >> 1) & 1u);
+    const bool act = lane < 4u && pa < ea && pb < eb;
+    float dd = mode == 0 ? __builtin_huge_valf() : 0.f;
+    if (act) {
+      V3<float> P[3], Q[3];
+      load_pair(&d, pa, pb, P, Q);
+      dd = sqrtf(mode == 0 ? tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr)
+                           : tri_tri_max_d2<float, false>(P, Q, nullptr, nullptr));
+    }
+    if (mode == 0) best = fminf(best, wave_min(dd) + delta);
+    else best = fmaxf(best, fmaxf(wave_max(dd) - delta, 0.f));
+  }
+  if (lane == 0) {
     SlotState& st = p.st[s];
     st.delta = delta;
     st.n_ties = 0;
     st.n_admitted = 0;
     st.key_pair = ~0ull;
-    float key;
-    if (d.mode == 0) {
-      float lo, up;
-      bounds_min(ra, rb, d.enhanced != 0, lo, up);
-      st.best = fbits(up + delta);
-      st.best32 = fbits(__builtin_huge_valf());
-      st.key_d = ~0ull;
-      key = lo;
-    } else {
-      float up, lo;
-      bounds_max(ra, rb, d.enhanced != 0, up, lo);
-      st.best = fbits(fmaxf(lo - delta, 0.f));
-      st.best32 = 0u;
-      st.key_d = 0ull;
-      key = up;
-    }
+    st.best = fbits(best);
+    st.best32 = mode == 0 ? fbits(__builtin_huge_valf()) : 0u;
+    st.key_d = mode == 0 ? ~0ull : 0ull;
     gdist_result_t& r = p.res[s];
     r.status = GDIST_E_DEVICE;
     r.flags = 0;
+    // root pairs enter round 0 through the segment of workgroup 0
     uint4 e = make_uint4(1u, 1u, fbits(key), s);
     if (d.LA == 1 && d.LB == 1) {
-      uint32_t i = atomicAdd(&c->leaf_len[0], 1u);
+      uint32_t i = atomicAdd(&p.lcount[0][0], 1u);
       p.leaf[0][i] = e;
     } else {
-      uint32_t i = atomicAdd(&c->front_len[0], 1u);
+      uint32_t i = atomicAdd(&p.fcount[0][0], 1u);
       p.front[0][i] = e;
     }
   }
 }
 
-// Expansion of one wave's worth of items of the current front.
-__device__ __forceinline__ void expand_wave(const TravParams& p, const uint4* __restrict__ fin,
-                                            uint4* __restrict__ fout, uint4* __restrict__ lout, uint32_t o3,
-                                            uint64_t it, uint64_t n_items, uint32_t k, unsigned long long* sst,
-                                            uint32_t lane, uint64_t lt) {
-  Ctl* c = p.ctl;
-  bool act = it < n_items;
-  const uint32_t kk = 2 * k;
-  uint4 ent = make_uint4(1u, 1u, 0u, 0u);
-  if (act) ent = fin[it >> kk];
-  const uint32_t sub = (uint32_t)(it & ((1ull << kk) - 1ull));
-  const uint32_t slot = ent.w;
-  const SlotDesc* d = p.desc + slot;
-  const uint32_t mode = d->mode;
-  const float delta = p.st[slot].delta;
-  const float best = bitsf(ld_rlx(&p.st[slot].best));
-  const float key = bitsf(ent.z);
-  if (act) act = mode == 0 ? !(key - delta > best) : !(key + delta < best);
-  const uint32_t remA = d->depthA - (31u - (uint32_t)__clz(ent.x));
-  const uint32_t remB = d->depthB - (31u - (uint32_t)__clz(ent.y));
-  uint32_t kA = remA < k ? remA : k;
-  uint32_t kB = remB < kk - kA ? remB : kk - kA;
-  kA = remA < kk - kB ? remA : kk - kB;
-  if (act) act = (sub >> (kA + kB)) == 0u;
-  add_stat(sst, ST_POPPED, act && sub == 0u, lane);
-  add_stat(sst, ST_CHILD, act, lane);
-  const uint32_t ca = (ent.x << kA) | (sub & ((1u << kA) - 1u));
-  const uint32_t cb = (ent.y << kB) | (sub >> kA);
-  bool keep = false;
-  float improve = 0.f, nkey = 0.f;
-  if (act) {
-    Box ba = load_box(d->boxA, ca), bb = load_box(d->boxB, cb);
-    const bool enh = d->enhanced != 0;
-    if (mode == 0) {
-      float lo, up;
-      bounds_min(ba, bb, enh, lo, up);
-      keep = lo - delta <= best;
-      improve = up + delta;
-      nkey = lo;
-    } else {
-      float up, lo;
-      bounds_max(ba, bb, enh, up, lo);
-      keep = up + delta >= best;
-      improve = fmaxf(lo - delta, 0.f);
-      nkey = up;
-    }
-  }
-  const bool isleaf = (ca >= d->LA) && (cb >= d->LB);
-  const uint4 ne = make_uint4(ca, cb, fbits(nkey), slot);
-  append(act && keep && isleaf, ne, lout, &c->leaf_len[o3], p.leaf_cap, &c->overflow, 2u, lane, lt);
-  append(act && keep && !isleaf, ne, fout, &c->front_len[o3], p.front_cap, &c->overflow, 1u, lane, lt);
-  add_stat(sst, ST_PUSHED, act && keep, lane);
-  improve_bound(&p.st[0].best, sizeof(SlotState) / 4, act, slot, mode, improve, lane);
+// Per-workgroup LDS state of the traversal.  Appends of a round go to the
+// workgroup's own segment of the output buffers, counted in LDS, so the hot
+// loop issues no global atomics; at the round's end each workgroup publishes
+// its counts, and the next round maps a global entry index to (segment,
+// offset) through an exclusive prefix sum over the workgroups' counts.
+constexpr uint32_t kMaxBlocks = 1024;
+constexpr uint32_t kLdsSlots = 512;
+
+struct BlockState {
+  uint32_t fpre[kMaxBlocks + 1];   // prefix of the current front's segment counts
+  uint32_t lpre[kMaxBlocks + 1];   // same for the leaf-pair buffer
+  uint32_t scan[kTravThreads];
+  uint32_t fo, lo;                 // this workgroup's appends in the current round
+  uint32_t best[kLdsSlots];        // per-slot running bound (float bits), refreshed each round
+  float delta[kLdsSlots];
+  unsigned long long stats[ST_N];
+};
+
+struct Round {
+  const uint4* fin;
+  uint4* fout;
+  const uint4* lin;
+  uint4* lout;
+  uint32_t nb, seg_f, seg_l;
+  bool lds_slots;
+};
+
+__device__ __forceinline__ float get_best(const TravParams& p, const BlockState* bs, bool lds, uint32_t slot) {
+  return bitsf(lds ? bs->best[slot] : ld_rlx(&p.st[slot].best));
+}
+__device__ __forceinline__ float get_delta(const TravParams& p, const BlockState* bs, bool lds, uint32_t slot) {
+  return lds ? bs->delta[slot] : p.st[slot].delta;
 }
 
-// Narrow phase for one wave: 4 lanes per leaf pair, one triangle pair each.
-__device__ __forceinline__ void narrow_wave(const TravParams& p, const uint4* __restrict__ lin, uint64_t it,
-                                            uint64_t n_items, unsigned long long* sst, uint32_t lane, uint64_t lt) {
+// Improve a slot's running bound in memory and in this workgroup's LDS copy.
+__device__ __forceinline__ void improve_best(const TravParams& p, BlockState* bs, bool lds, bool act,
+                                             uint32_t slot, uint32_t mode, float v, uint32_t lane) {
+  if (!__ballot(act)) return;
+  improve_bound(&p.st[0].best, sizeof(SlotState) / 4, act, slot, mode, v, lane);
+  if (lds && act) {
+    if (mode == 0) atomicMin(&bs->best[slot], fbits(v));
+    else atomicMax(&bs->best[slot], fbits(v));
+  }
+}
+
+// Largest segment s with pre[s] <= e; the entry's address is s*seg + e - pre[s].
+__device__ __forceinline__ uint32_t seg_addr(const uint32_t* pre, uint32_t nb, uint32_t seg, uint32_t e) {
+  uint32_t lo = 0, hi = nb;
+  while (hi - lo > 1u) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (pre[mid] <= e) lo = mid;
+    else hi = mid;
+  }
+  return lo * seg + (e - pre[lo]);
+}
+
+// Exclusive prefix over nb <= 4 * kTravThreads counts; pre[nb] = total.
+__device__ __forceinline__ void block_prefix(const uint32_t* cnt, uint32_t nb, uint32_t* pre, uint32_t* tmp) {
+  const uint32_t t = threadIdx.x;
+  uint32_t v[4], s = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    uint32_t idx = 4u * t + i;
+    v[i] = idx < nb ? cnt[idx] : 0u;
+    s += v[i];
+  }
+  tmp[t] = s;
+  __syncthreads();
+  for (uint32_t off = 1; off < kTravThreads; off <<= 1) {
+    uint32_t x = t >= off ? tmp[t - off] : 0u;
+    __syncthreads();
+    tmp[t] += x;
+    __syncthreads();
+  }
+  uint32_t run = tmp[t] - s;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    uint32_t idx = 4u * t + i;
+    if (idx < nb) pre[idx] = run;
+    run += v[i];
+  }
+  if (t == kTravThreads - 1) pre[nb] = tmp[t];
+  __syncthreads();
+}
+
+// Append the lanes flagged in R rows to this workgroup's segment of `buf`
+// with one LDS atomic: row r's lanes land after the survivors of rows 0..r-1.
+template <int R>
+__device__ __forceinline__ void append_rows(const bool* take, const uint4* e, uint4* buf, uint32_t seg,
+                                            uint32_t* lds_count, uint32_t* overflow, uint32_t ovf_bit, uint32_t lane,
+                                            uint64_t lt) {
+  uint64_t m[R];
+  uint32_t tot = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    m[r] = __ballot(take[r]);
+    tot += (uint32_t)__popcll(m[r]);
+  }
+  if (tot == 0u) return;
+  uint32_t base = 0;
+  if (lane == 0) {
+    base = atomicAdd(lds_count, tot);
+    if (base + tot > seg) atomicOr(overflow, ovf_bit);
+  }
+  base = __shfl(base, 0, 64);
+  uint4* out = buf + (uint64_t)blockIdx.x * seg;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (take[r]) {
+      uint32_t idx = base + (uint32_t)__popcll(m[r] & lt);
+      if (idx < seg) out[idx] = e[r];
+    }
+    base += (uint32_t)__popcll(m[r]);
+  }
+}
+
+// Expansion of R consecutive waves' worth of items of the current front
+// (items it0 + 64 r + lane).  All loads of the R rows are issued before any
+// result is needed, and the survivors of the R rows are appended together.
+template <int R>
+__device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs, const Round& rd, uint64_t it0,
+                                            uint64_t n_items, uint32_t k, uint32_t lane, uint64_t lt) {
   Ctl* c = p.ctl;
+  const uint32_t kk = 2 * k;
+  uint4 ent[R];
+  bool act[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t it = it0 + 64ull * r;
+    act[r] = it < n_items;
+    ent[r] = act[r] ? rd.fin[seg_addr(bs->fpre, rd.nb, rd.seg_f, (uint32_t)(it >> kk))] : make_uint4(1u, 1u, 0u, 0u);
+  }
+  bool to_leaf[R], to_front[R];
+  uint4 ne[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint64_t it = it0 + 64ull * r;
+    const uint32_t sub = (uint32_t)(it & ((1ull << kk) - 1ull));
+    const uint32_t slot = ent[r].w;
+    const SlotDesc* d = p.desc + slot;
+    const uint32_t mode = d->mode;
+    const float delta = get_delta(p, bs, rd.lds_slots, slot);
+    const float best = get_best(p, bs, rd.lds_slots, slot);
+    const float key = bitsf(ent[r].z);
+    bool a = act[r] && (mode == 0 ? !(key - delta > best) : !(key + delta < best));
+    uint32_t kA, kB;
+    split_levels(d->depthA - level_of(ent[r].x), d->depthB - level_of(ent[r].y), kk, kA, kB);
+    a = a && (sub >> (kA + kB)) == 0u;
+    add_stat(bs->stats, ST_POPPED, a && sub == 0u, lane);
+    add_stat(bs->stats, ST_CHILD, a, lane);
+    const uint32_t ca = (ent[r].x << kA) | (sub & ((1u << kA) - 1u));
+    const uint32_t cb = (ent[r].y << kB) | (sub >> kA);
+    bool keep = false;
+    float improve = 0.f, nkey = 0.f;
+    if (a) {
+      Box ba = load_box(d->boxA, ca), bb = load_box(d->boxB, cb);
+      const bool enh = d->enhanced != 0;
+      if (mode == 0) {
+        float lo, up;
+        bounds_min(ba, bb, enh, lo, up);
+        keep = lo - delta <= best;
+        improve = up + delta;
+        nkey = lo;
+      } else {
+        float up, lo;
+        bounds_max(ba, bb, enh, up, lo);
+        keep = up + delta >= best;
+        improve = fmaxf(lo - delta, 0.f);
+        nkey = up;
+      }
+    }
+    const bool isleaf = (ca >= d->LA) && (cb >= d->LB);
+    ne[r] = make_uint4(ca, cb, fbits(nkey), slot);
+    to_leaf[r] = a && keep && isleaf;
+    to_front[r] = a && keep && !isleaf;
+    add_stat(bs->stats, ST_PUSHED, a && keep, lane);
+    // only a value that beats the bound this lane already saw can help
+    const bool helps = a && (mode == 0 ? improve < best : improve > best);
+    improve_best(p, bs, rd.lds_slots, helps, slot, mode, improve, lane);
+  }
+  append_rows<R>(to_leaf, ne, rd.lout, rd.seg_l, &bs->lo, &c->overflow, 2u, lane, lt);
+  append_rows<R>(to_front, ne, rd.fout, rd.seg_f, &bs->fo, &c->overflow, 1u, lane, lt);
+}
+
+// Narrow phase, stage 1: one lane per leaf pair.  The lane loads the leaf
+// pair's 1-2 triangles of each side once, gives each of the (up to 4)
+// triangle pairs the cheap separating-axis test, and pushes the survivors
+// onto the wave's LDS queue (at most 4 x 64 per call).
+__device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockState* bs, const Round& rd, uint64_t it,
+                                                   uint64_t n_items, uint32_t lane, uint64_t lt, uint4* q,
+                                                   uint32_t& qn) {
   bool act = it < n_items;
   uint4 ent = make_uint4(1u, 1u, 0u, 0u);
-  if (act) ent = lin[it >> 2];
-  const uint32_t s4 = (uint32_t)(it & 3ull);
+  if (act) ent = rd.lin[seg_addr(bs->lpre, rd.nb, rd.seg_l, (uint32_t)it)];
   const uint32_t slot = ent.w;
   const SlotDesc* d = p.desc + slot;
   const uint32_t mode = d->mode;
-  const float delta = p.st[slot].delta;
-  const float best = bitsf(ld_rlx(&p.st[slot].best));
+  const float delta = get_delta(p, bs, rd.lds_slots, slot);
+  const float best = get_best(p, bs, rd.lds_slots, slot);
   const float key = bitsf(ent.z);
   if (act) act = mode == 0 ? !(key - delta > best) : !(key + delta < best);
-  add_stat(sst, ST_LEAF, act && s4 == 0u, lane);
-  const uint32_t LA = d->LA, LB = d->LB, nA = d->nA, nB = d->nB;
-  const uint32_t ja = ent.x - LA, jb = ent.y - LB;
-  const uint32_t sa = (uint32_t)(((uint64_t)ja * nA) / LA), ea = (uint32_t)(((uint64_t)(ja + 1) * nA) / LA);
-  const uint32_t sb = (uint32_t)(((uint64_t)jb * nB) / LB), eb = (uint32_t)(((uint64_t)(jb + 1) * nB) / LB);
-  const uint32_t pa = sa + (s4 & 1u), pb = sb + (s4 >> 1);
-  if (act) act = pa < ea && pb < eb;
-  float dd = 0.f;
-  bool cand = false;
-  float improve = 0.f;
+  add_stat(bs->stats, ST_LEAF, act, lane);
+  uint32_t sa = 0, ea = 0, sb = 0, eb = 0;
   if (act) {
-    float P[9], Q[9];
-    load_tri(d->trisA, pa, P);
-    load_tri_xf(d->trisB, pb, d->T, Q);
-    V3<float> Pv[3], Qv[3];
+    leaf_range(ent.x, d->depthA, d->nA, sa, ea);
+    leaf_range(ent.y, d->depthB, d->nB, sb, eb);
+  }
+  V3<float> P[2][3], Q[2][3];
+  if (act && mode == 0) {
 #pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      Pv[v] = mk<float>(P[3 * v], P[3 * v + 1], P[3 * v + 2]);
-      Qv[v] = mk<float>(Q[3 * v], Q[3 * v + 1], Q[3 * v + 2]);
+    for (int i = 0; i < 2; ++i) {
+      float a[9], b[9];
+      const uint32_t ia = sa + i < ea ? sa + i : sa;
+      const uint32_t ib = sb + i < eb ? sb + i : sb;
+      load_tri(d->trisA, ia, a);
+      load_tri_xf(d->trisB, ib, d->T, b);
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        P[i][v] = mk<float>(a[3 * v], a[3 * v + 1], a[3 * v + 2]);
+        Q[i][v] = mk<float>(b[3 * v], b[3 * v + 1], b[3 * v + 2]);
+      }
     }
-    float d2 = mode == 0 ? tri_tri_min_d2<float, false>(Pv, Qv, nullptr, nullptr)
-                         : tri_tri_max_d2<float, false>(Pv, Qv, nullptr, nullptr);
-    dd = sqrtf(d2);
+  }
+#pragma unroll
+  for (int s4 = 0; s4 < 4; ++s4) {
+    const uint32_t pa = sa + (s4 & 1), pb = sb + (s4 >> 1);
+    const bool valid = act && pa < ea && pb < eb;
+    bool pass = valid;
+    if (valid && mode == 0) pass = sep_lower(P[s4 & 1], Q[s4 >> 1]) - delta <= best;
+    add_stat(bs->stats, ST_TRI, valid, lane);
+    uint64_t m = __ballot(pass);
+    if (pass) q[qn + (uint32_t)__popcll(m & lt)] = make_uint4(slot, pa, pb, 0u);
+    qn += (uint32_t)__popcll(m);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Narrow phase, stage 2: exact FP32 triangle-triangle distance on queued pairs.
+__device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs, bool lds, uint4 e, bool act,
+                                            uint32_t lane, uint64_t lt) {
+  Ctl* c = p.ctl;
+  const uint32_t slot = e.x, pa = e.y, pb = e.z;
+  const SlotDesc* d = p.desc + slot;
+  const uint32_t mode = d->mode;
+  const float delta = get_delta(p, bs, lds, slot);
+  float dd = 0.f, improve = 0.f;
+  bool cand = false;
+  if (act) {
+    V3<float> P[3], Q[3];
+    load_pair(d, pa, pb, P, Q);
+    dd = sqrtf(mode == 0 ? tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr)
+                         : tri_tri_max_d2<float, false>(P, Q, nullptr, nullptr));
+    const float best = get_best(p, bs, lds, slot);
     if (mode == 0) {
       improve = dd + delta;
       cand = dd - delta <= best;
@@ -282,15 +578,15 @@ __device__ __forceinline__ void narrow_wave(const TravParams& p, const uint4* __
       cand = dd + delta >= best;
     }
   }
-  add_stat(sst, ST_TRI, act, lane);
+  add_stat(bs->stats, ST_FULL, act, lane);
   Cand ce;
   ce.d32 = dd;
   ce.slot = slot;
   ce.ia = pa;
   ce.ib = pb;
   append(act && cand, ce, p.cand, &c->cand_len, p.cand_cap, &c->overflow, 4u, lane, lt);
-  add_stat(sst, ST_CAND, act && cand, lane);
-  improve_bound(&p.st[0].best, sizeof(SlotState) / 4, act, slot, mode, improve, lane);
+  add_stat(bs->stats, ST_CAND, act && cand, lane);
+  improve_best(p, bs, lds, act, slot, mode, improve, lane);
   improve_bound(&p.st[0].best32, sizeof(SlotState) / 4, act, slot, mode, dd, lane);
 }
 
@@ -308,53 +604,97 @@ __device__ __forceinline__ void world_tri(const float* tris, uint32_t pos, const
 }
 
 __global__ __launch_bounds__(kTravThreads) void k_traverse(TravParams p) {
-  __shared__ unsigned long long sst[ST_N];
-  if (threadIdx.x < ST_N) sst[threadIdx.x] = 0ull;
-  __syncthreads();
+  __shared__ BlockState bs_;
+  __shared__ uint4 sq[kWavesPerBlock][kQueue];
+  BlockState* bs = &bs_;
   Ctl* c = p.ctl;
-  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u;
   const uint64_t lt = (1ull << lane) - 1ull;
-  const uint64_t wpb = blockDim.x >> 6;
-  const uint64_t gw = (uint64_t)blockIdx.x * wpb + (threadIdx.x >> 6);
-  const uint64_t nw = (uint64_t)gridDim.x * wpb;
+  const uint32_t wib = tid >> 6;
+  const uint64_t gw = (uint64_t)blockIdx.x * kWavesPerBlock + wib;
+  const uint64_t nw = (uint64_t)gridDim.x * kWavesPerBlock;
+  uint4* q = sq[wib];
+  const bool lds_slots = p.n_slots <= kLdsSlots;
+  if (tid < ST_N) bs->stats[tid] = 0ull;
+  if (tid == 0) {
+    bs->fo = 0u;
+    bs->lo = 0u;
+  }
+  if (lds_slots)
+    for (uint32_t s = tid; s < p.n_slots; s += kTravThreads) bs->delta[s] = p.st[s].delta;
 
   for (uint32_t round = 0;; ++round) {
-    const uint32_t r3 = round % 3u, o3 = (round + 1u) % 3u;
     if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) break;
-    uint32_t n = ld_rlx(&c->front_len[r3]);
-    uint32_t nl = ld_rlx(&c->leaf_len[r3]);
+    Round rd;
+    rd.nb = gridDim.x;
+    rd.seg_f = p.seg_front;
+    rd.seg_l = p.seg_leaf;
+    rd.lds_slots = lds_slots;
+    rd.fin = p.front[round & 1u];
+    rd.fout = p.front[(round + 1u) & 1u];
+    rd.lin = p.leaf[round & 1u];
+    rd.lout = p.leaf[(round + 1u) & 1u];
+    if (lds_slots)
+      for (uint32_t s = tid; s < p.n_slots; s += kTravThreads) bs->best[s] = ld_rlx(&p.st[s].best);
+    block_prefix(p.fcount[round & 1u], rd.nb, bs->fpre, bs->scan);
+    block_prefix(p.lcount[round & 1u], rd.nb, bs->lpre, bs->scan);
+    const uint32_t n = bs->fpre[rd.nb];
+    const uint32_t nl = bs->lpre[rd.nb];
     if (n == 0u && nl == 0u) break;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st_rlx(&c->front_len[(round + 2u) % 3u], 0u);
-      st_rlx(&c->leaf_len[(round + 2u) % 3u], 0u);
-      sst[ST_ROUNDS] += 1ull;
-      if (n > sst[ST_PEAK]) sst[ST_PEAK] = n;
+    if (blockIdx.x == 0 && tid == 0) {
+      bs->stats[ST_ROUNDS] += 1ull;
+      if (n > bs->stats[ST_PEAK]) bs->stats[ST_PEAK] = n;
+      if (round < kTraceRounds) {
+        c->trace_t[round] = (unsigned long long)wall_clock64();
+        c->trace_n[round] = n;
+        c->trace_nl[round] = nl;
+      }
     }
     uint32_t k = p.k_cap;
     while (k > 1u && ((uint64_t)n << (2u * k)) >= (uint64_t)p.expand_budget) --k;
-    const uint64_t leaf_items = (uint64_t)nl * 4ull;
+    const uint64_t leaf_items = (uint64_t)nl;   // one lane per leaf pair
     const uint64_t leaf_waves = (leaf_items + 63ull) >> 6;
     const uint64_t exp_items = (uint64_t)n << (2u * k);
-    const uint64_t total = leaf_waves + ((exp_items + 63ull) >> 6);
-    const uint4* fin = p.front[round & 1u];
-    uint4* fout = p.front[(round + 1u) & 1u];
-    const uint4* lin = p.leaf[round & 1u];
-    uint4* lout = p.leaf[(round + 1u) & 1u];
-    for (uint64_t w = gw; w < total; w += nw) {
-      if (w < leaf_waves) narrow_wave(p, lin, w * 64ull + lane, leaf_items, sst, lane, lt);
-      else expand_wave(p, fin, fout, lout, o3, (w - leaf_waves) * 64ull + lane, exp_items, k, sst, lane, lt);
+    // expansion work is handed out in groups of kRows waves' worth of items
+    const uint64_t total = leaf_waves + ((exp_items + 64ull * kRows - 1ull) / (64ull * kRows));
+    uint32_t qn = 0;  // wave-uniform fill of this wave's LDS queue
+    for (uint64_t w = gw;;) {
+      const bool more = w < total;
+      if (more) {
+        if (w < leaf_waves) narrow_filter_wave(p, bs, rd, w * 64ull + lane, leaf_items, lane, lt, q, qn);
+        else expand_rows<kRows>(p, bs, rd, (w - leaf_waves) * 64ull * kRows + lane, exp_items, k, lane, lt);
+        w += nw;
+      }
+      while (qn >= 64u || (!more && qn > 0u)) {
+        const uint32_t take = qn >= 64u ? 64u : qn;
+        qn -= take;
+        const bool a = lane < take;
+        const uint4 e = q[qn + (a ? lane : 0u)];
+        __builtin_amdgcn_wave_barrier();
+        narrow_full(p, bs, lds_slots, e, a, lane, lt);
+      }
+      if (!more) break;
+    }
+    // publish this workgroup's output counts for the next round
+    __syncthreads();
+    if (tid == 0) {
+      p.fcount[(round + 1u) & 1u][blockIdx.x] = bs->fo < rd.seg_f ? bs->fo : rd.seg_f;
+      p.lcount[(round + 1u) & 1u][blockIdx.x] = bs->lo < rd.seg_l ? bs->lo : rd.seg_l;
+      bs->fo = 0u;
+      bs->lo = 0u;
     }
     grid_sync(c, p.spin_limit);
   }
+  if (blockIdx.x == 0 && tid == 0) c->trace_end = (unsigned long long)wall_clock64();
 
   __syncthreads();
-  if (threadIdx.x < ST_N && sst[threadIdx.x]) {
-    if (threadIdx.x == ST_PEAK) atomicMax(&c->stats[ST_PEAK], sst[ST_PEAK]);
-    else if (threadIdx.x == ST_ROUNDS) atomicMax(&c->stats[ST_ROUNDS], sst[ST_ROUNDS]);
-    else atomicAdd(&c->stats[threadIdx.x], sst[threadIdx.x]);
+  if (tid < ST_N && bs->stats[tid]) {
+    if (tid == ST_PEAK) atomicMax(&c->stats[ST_PEAK], bs->stats[ST_PEAK]);
+    else if (tid == ST_ROUNDS) atomicMax(&c->stats[ST_ROUNDS], bs->stats[ST_ROUNDS]);
+    else atomicAdd(&c->stats[tid], bs->stats[tid]);
   }
 }
-
 
 // FP64 re-evaluation, in three grid-wide steps (separate launches).
 // A: admit the candidates inside the final window and evaluate them in FP64
@@ -466,7 +806,8 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_report(TravParams p) {
 }
 
 hipError_t launch_init(const TravParams& p, hipStream_t s) {
-  k_init<<<1, 256, 0, s>>>(p);
+  k_reset<<<1, 256, 0, s>>>(p);
+  k_init<<<(p.n_slots + kWavesPerBlock - 1) / kWavesPerBlock, kTravThreads, 0, s>>>(p);
   return hipGetLastError();
 }
 
@@ -480,7 +821,9 @@ hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, u
   uint32_t b = (uint32_t)per_cu;
   if (blocks_per_cu > 0 && blocks_per_cu < b) b = blocks_per_cu;
   if (b == 0) b = 1;
-  *blocks = b * (uint32_t)prop.multiProcessorCount;
+  uint32_t total = b * (uint32_t)prop.multiProcessorCount;
+  if (total > kMaxBlocks) total = kMaxBlocks;   // the per-round prefix lives in LDS
+  *blocks = total;
   *threads = kTravThreads;
   return hipSuccess;
 }

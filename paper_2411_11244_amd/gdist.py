@@ -62,7 +62,7 @@ class gdist_mesh_info_t(C.Structure):
 class gdist_stats_t(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "rounds", "entries_popped", "child_pairs", "entries_pushed", "leaf_pairs", "tri_pairs",
-        "candidates", "front_peak", "bytes_refit", "bytes_traversal", "bytes_narrow", "retries")] + \
+        "tri_full", "candidates", "front_peak", "bytes_refit", "bytes_traversal", "bytes_narrow", "retries")] + \
                [("ms_refit", C.c_double), ("ms_traversal", C.c_double), ("ms_total", C.c_double)]
 
     def as_dict(self) -> dict:
