@@ -65,7 +65,9 @@ struct gdist_ctx {
   double kappa = 64.0;
   uint64_t memory_budget = 0, bytes_held = 0;
   // workspace
-  DevBuf ws_boxes, front[2], leaf[2], counts, cand, cand64, ctl, desc, st, res;
+  DevBuf ws_boxes, front[2], leaf[2], counts, cand, cand64, ctl, desc, st, res, refit_tab;
+  void* pinned = nullptr;       // host staging for descriptors and job tables
+  size_t pinned_bytes = 0;
   uint32_t trav_blocks = 0, trav_threads = 0;
   int wall_khz = 0;
   bool trace = false;
@@ -108,6 +110,22 @@ gdist_status_t ensure(gdist_ctx* c, DevBuf& b, size_t bytes) {
   gdist_status_t s = dalloc(c, bytes, &b.p);
   if (s != GDIST_OK) return s;
   b.bytes = bytes;
+  return GDIST_OK;
+}
+
+gdist_status_t ensure_pinned(gdist_ctx* c, size_t bytes) {
+  if (c->pinned_bytes >= bytes && c->pinned) return GDIST_OK;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  c->pinned = nullptr;
+  c->pinned_bytes = 0;
+  size_t want = bytes < (1u << 16) ? (1u << 16) : bytes;
+  if (hipHostMalloc(&c->pinned, want, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    c->pinned = nullptr;
+    return fail(GDIST_E_OOM, "hipHostMalloc(%zu) failed", want);
+  }
+  c->pinned_bytes = want;
   return GDIST_OK;
 }
 
@@ -351,15 +369,32 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
   if ((s = ensure(c, c->st, sizeof(SlotState) * n)) != GDIST_OK) return s;
   if ((s = ensure(c, c->res, sizeof(gdist_result_t) * n)) != GDIST_OK) return s;
   if ((s = ensure(c, c->ctl, sizeof(Ctl))) != GDIST_OK) return s;
-  HIPCHK(hipMemcpyAsync(c->desc.p, desc.data(), sizeof(SlotDesc) * n, hipMemcpyHostToDevice, c->stream));
+  // descriptors and refit job tables go through pinned staging (async H2D)
+  std::vector<RefitJob> jobs(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    const Mesh* B = plan[i].B;
+    std::memset(&jobs[i], 0, sizeof(RefitJob));
+    jobs[i].tris = B->tris;
+    jobs[i].boxes = (float*)c->ws_boxes.p + plan[i].box_off;
+    jobs[i].T = desc[i].T;
+    jobs[i].n = B->n_tris;
+    jobs[i].L = B->L;
+  }
+  const size_t desc_bytes = (sizeof(SlotDesc) * n + 255) & ~(size_t)255;
+  const size_t tab_cap = sizeof(RefitJob) * n + sizeof(ReduceJob) * n * kMaxRefitPasses + 256;
+  if ((s = ensure_pinned(c, desc_bytes + tab_cap)) != GDIST_OK) return s;
+  std::memcpy(c->pinned, desc.data(), sizeof(SlotDesc) * n);
+  RefitPlan rplan;
+  const size_t tab_bytes = plan_refit_batch(jobs.data(), n, (char*)c->pinned + desc_bytes, tab_cap, &rplan);
+  if (tab_bytes == 0) return fail(GDIST_E_INVALID, "refit plan does not fit (%u queries)", n);
+  if ((s = ensure(c, c->refit_tab, tab_bytes)) != GDIST_OK) return s;
+  HIPCHK(hipMemcpyAsync(c->desc.p, c->pinned, sizeof(SlotDesc) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->refit_tab.p, (char*)c->pinned + desc_bytes, tab_bytes, hipMemcpyHostToDevice, c->stream));
 
   std::memset(&c->last, 0, sizeof(c->last));
   HIPCHK(hipEventRecord(c->ev[0], c->stream));
-  for (uint32_t i = 0; i < n; ++i) {
-    const Mesh* B = plan[i].B;
-    HIPCHK(launch_refit(B->tris, B->n_tris, B->L, desc[i].T, (float*)c->ws_boxes.p + plan[i].box_off, c->stream));
-    c->last.bytes_refit += 36ull * B->n_tris + 24ull * (2ull * B->L - 1ull);
-  }
+  HIPCHK(launch_refit_batch(rplan, c->refit_tab.p, c->stream));
+  for (uint32_t i = 0; i < n; ++i) c->last.bytes_refit += 36ull * plan[i].B->n_tris + 24ull * (2ull * plan[i].B->L - 1ull);
   HIPCHK(hipEventRecord(c->ev[1], c->stream));
 
   // Traversal in groups of slots.  A group whose storage overflows first
@@ -451,7 +486,8 @@ gdist_status_t gdist_destroy(gdist_ctx_t c) {
     delete m;
   }
   c->meshes.clear();
-  DevBuf* bufs[] = {&c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->counts, &c->cand,
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  DevBuf* bufs[] = {&c->refit_tab, &c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->counts, &c->cand,
                     &c->cand64, &c->ctl, &c->desc, &c->st, &c->res};
   for (DevBuf* b : bufs) release_buf(c, *b);
   for (int i = 0; i < 4; ++i)

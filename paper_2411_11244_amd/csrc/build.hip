@@ -139,26 +139,73 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t* __restri
   hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// In-place exclusive scan of `len` counts by one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ a, uint64_t len) {
-  __shared__ uint32_t s[1024];
-  uint64_t chunk = (len + 1023) / 1024;
-  uint64_t b = threadIdx.x * chunk, e = b + chunk < len ? b + chunk : len;
-  uint32_t sum = 0;
-  for (uint64_t i = b; i < e; ++i) sum += a[i];
-  s[threadIdx.x] = sum;
+// Exclusive scan of `len` counts in three launches: tile sums, a scan of the
+// tile sums, and the in-place rescan of each tile with its offset.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr uint64_t kScanTile = (uint64_t)kScanThreads * kScanItems;  // 4096 counts per workgroup
+
+// Exclusive scan of one value per thread across the workgroup; returns the
+// workgroup total.
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* s, uint32_t* excl) {
+  const uint32_t t = threadIdx.x;
+  s[t] = v;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t x = threadIdx.x >= (uint32_t)off ? s[threadIdx.x - off] : 0u;
+  for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
+    uint32_t x = t >= off ? s[t - off] : 0u;
     __syncthreads();
-    s[threadIdx.x] += x;
+    s[t] += x;
     __syncthreads();
   }
-  uint32_t run = s[threadIdx.x] - sum;  // exclusive prefix of this chunk
-  for (uint64_t i = b; i < e; ++i) {
-    uint32_t x = a[i];
-    a[i] = run;
-    run += x;
+  *excl = s[t] - v;
+  uint32_t total = s[kScanThreads - 1];
+  __syncthreads();
+  return total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const uint32_t* __restrict__ a, uint64_t len,
+                                                             uint32_t* __restrict__ tile_sum) {
+  __shared__ uint32_t s[kScanThreads];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  uint32_t v = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < len) v += a[base + i];
+  uint32_t excl;
+  uint32_t total = block_exclusive(v, s, &excl);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// One workgroup scans the tile sums in place (exclusive).
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(uint32_t* __restrict__ tile_sum, uint32_t n) {
+  __shared__ uint32_t s[kScanThreads];
+  uint32_t carry = 0;
+  for (uint32_t b = 0; b < n; b += kScanThreads) {
+    const uint32_t i = b + threadIdx.x;
+    uint32_t v = i < n ? tile_sum[i] : 0u, excl;
+    uint32_t total = block_exclusive(v, s, &excl);
+    if (i < n) tile_sum[i] = carry + excl;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t* __restrict__ a, uint64_t len,
+                                                             const uint32_t* __restrict__ tile_sum) {
+  __shared__ uint32_t s[kScanThreads];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems], sum = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < len ? a[base + i] : 0u;
+    sum += v[i];
+  }
+  uint32_t excl;
+  block_exclusive(sum, s, &excl);
+  uint32_t run = tile_sum[blockIdx.x] + excl;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < len) a[base + i] = run;
+    run += v[i];
   }
 }
 
@@ -256,16 +303,25 @@ hipError_t launch_morton(const float* v, const uint32_t* f, uint32_t nt, const i
   return hipGetLastError();
 }
 
-size_t radix_hist_words(uint32_t n) { return (size_t)256 * ((n + kRsTile - 1) / kRsTile); }
+// histogram words plus the scan's tile sums
+size_t radix_hist_words(uint32_t n) {
+  uint64_t h = (uint64_t)256 * ((n + kRsTile - 1) / kRsTile);
+  return (size_t)(h + (h + kScanTile - 1) / kScanTile);
+}
 
 hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
                              uint32_t n, uint32_t* hist, hipStream_t s, int* result_in_tmp) {
   uint32_t nblocks = (n + kRsTile - 1) / kRsTile;
+  const uint64_t hlen = (uint64_t)256 * nblocks;
+  const uint32_t tiles = (uint32_t)((hlen + kScanTile - 1) / kScanTile);
+  uint32_t* tile_sum = hist + hlen;
   uint64_t *ki = keys, *ko = keys_tmp;
   uint32_t *vi = vals, *vo = vals_tmp;
   for (uint32_t shift = 0; shift < 64; shift += 8) {
     k_rs_hist<<<nblocks, kRsThreads, 0, s>>>(ki, n, shift, hist, nblocks);
-    k_rs_scan<<<1, 1024, 0, s>>>(hist, (uint64_t)256 * nblocks);
+    k_scan_tiles<<<tiles, kScanThreads, 0, s>>>(hist, hlen, tile_sum);
+    k_scan_sums<<<1, kScanThreads, 0, s>>>(tile_sum, tiles);
+    k_scan_apply<<<tiles, kScanThreads, 0, s>>>(hist, hlen, tile_sum);
     k_rs_scatter<<<nblocks, kRsThreads, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblocks);
     uint64_t* tk = ki; ki = ko; ko = tk;
     uint32_t* tv = vi; vi = vo; vo = tv;

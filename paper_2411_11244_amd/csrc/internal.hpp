@@ -108,6 +108,28 @@ hipError_t launch_emit(const float* v, const uint32_t* f, uint32_t nt, const uin
 // refit.hip
 hipError_t launch_refit(const float* tris, uint32_t n, uint32_t L, const Xf32& T, float* boxes, hipStream_t s);
 
+// One tree of a batched refit: its triangles (leaf order), its output boxes,
+// the transform; S and first_block are filled by the planner.
+struct RefitJob {
+  const float* tris;
+  float* boxes;
+  Xf32 T;
+  uint32_t n, L, S, first_block;
+};
+struct ReduceJob {
+  float* boxes;
+  uint32_t first, S, first_block, pad;
+};
+constexpr uint32_t kMaxRefitPasses = 8;
+struct RefitPlan {
+  size_t leaf_off;
+  uint32_t leaf_blocks, njobs, npasses;
+  size_t pass_off[kMaxRefitPasses];
+  uint32_t pass_jobs[kMaxRefitPasses], pass_blocks[kMaxRefitPasses];
+};
+size_t plan_refit_batch(const RefitJob* in, uint32_t njobs, void* staging, size_t cap, RefitPlan* plan);
+hipError_t launch_refit_batch(const RefitPlan& plan, const void* dev, hipStream_t s);
+
 // traverse.hip
 hipError_t launch_init(const TravParams& p, hipStream_t s);
 hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, uint32_t* threads);

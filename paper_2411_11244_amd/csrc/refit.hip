@@ -9,6 +9,8 @@
 // writing every node of the subtree once.  The remaining upper levels are
 // reduced by the same LDS scheme over the subtree roots.  Per triangle the
 // kernel reads 36 B; per node it writes 24 B.
+#include <vector>
+
 #include "internal.hpp"
 
 namespace gd {
@@ -80,6 +82,157 @@ __global__ __launch_bounds__(kRefitThreads) void k_reduce_levels(float* __restri
       store_box(boxes, base + j, nb);
     }
   }
+}
+
+// ------------------------------------------------------------------ batched
+// Many trees refitted by one launch per pass.  Workgroup b serves the job j
+// with first_block[j] <= b < first_block[j+1] (binary search in thread 0).
+template <typename J>
+__device__ __forceinline__ const J* find_job(const J* jobs, uint32_t njobs) {
+  __shared__ uint32_t s_job;
+  if (threadIdx.x == 0) {
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1u) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (jobs[mid].first_block <= blockIdx.x) lo = mid;
+      else hi = mid;
+    }
+    s_job = lo;
+  }
+  __syncthreads();
+  return jobs + s_job;
+}
+
+__global__ __launch_bounds__(kRefitThreads) void k_refit_leaves_batch(const RefitJob* __restrict__ jobs,
+                                                                       uint32_t njobs) {
+  __shared__ Box lb[kRefitThreads];
+  const RefitJob* jp = find_job(jobs, njobs);
+  const RefitJob J = *jp;
+  const uint32_t j = threadIdx.x;
+  const uint32_t blk = blockIdx.x - J.first_block;
+  const uint32_t S = J.S, L = J.L, n = J.n;
+  if (j < S) {
+    Box b;
+    uint32_t leaf = blk * S + j;
+    const uint32_t D = 31u - (uint32_t)__clz(L);
+    uint32_t start = (uint32_t)(((uint64_t)leaf * n) >> D);
+    uint32_t end = (uint32_t)(((uint64_t)(leaf + 1) * n) >> D);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      b.lo[k] = __builtin_huge_valf();
+      b.hi[k] = -__builtin_huge_valf();
+    }
+    for (uint32_t p = start; p < end; ++p) {
+      float t[9];
+      load_tri_xf(J.tris, p, J.T, t);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          b.lo[k] = fminf(b.lo[k], t[3 * c + k]);
+          b.hi[k] = fmaxf(b.hi[k], t[3 * c + k]);
+        }
+    }
+    store_box(J.boxes, L + leaf, b);
+    lb[j] = b;
+  }
+  uint32_t base = L + blk * S;
+  for (uint32_t cnt = S; cnt > 1; cnt >>= 1) {
+    __syncthreads();
+    Box nb;
+    bool act = j < cnt / 2;
+    if (act) nb = box_union(lb[2 * j], lb[2 * j + 1]);
+    __syncthreads();
+    base >>= 1;
+    if (act) {
+      lb[j] = nb;
+      store_box(J.boxes, base + j, nb);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kRefitThreads) void k_reduce_batch(const ReduceJob* __restrict__ jobs, uint32_t njobs) {
+  __shared__ Box lb[kRefitThreads];
+  const ReduceJob J = *find_job(jobs, njobs);
+  const uint32_t j = threadIdx.x;
+  const uint32_t blk = blockIdx.x - J.first_block;
+  if (j < J.S) lb[j] = load_box(J.boxes, J.first + blk * J.S + j);
+  uint32_t base = J.first + blk * J.S;
+  for (uint32_t cnt = J.S; cnt > 1; cnt >>= 1) {
+    __syncthreads();
+    Box nb;
+    bool act = j < cnt / 2;
+    if (act) nb = box_union(lb[2 * j], lb[2 * j + 1]);
+    __syncthreads();
+    base >>= 1;
+    if (act) {
+      lb[j] = nb;
+      store_box(J.boxes, base + j, nb);
+    }
+  }
+}
+
+// Plan the passes of a batched refit.  Writes the job tables into `staging`
+// (host, pinned), returns their byte size; the tables are then copied to
+// `dev` and the passes launched by launch_refit_batch.
+size_t plan_refit_batch(const RefitJob* in, uint32_t njobs, void* staging, size_t cap, RefitPlan* plan) {
+  char* out = (char*)staging;
+  size_t used = 0;
+  auto need = [&](size_t b) { return used + b <= cap; };
+  plan->npasses = 0;
+  // leaves
+  if (!need(sizeof(RefitJob) * njobs)) return 0;
+  RefitJob* lj = (RefitJob*)(out + used);
+  uint32_t blocks = 0;
+  std::vector<uint32_t> count(njobs);
+  for (uint32_t i = 0; i < njobs; ++i) {
+    lj[i] = in[i];
+    lj[i].S = in[i].L < (uint32_t)kRefitThreads ? in[i].L : (uint32_t)kRefitThreads;
+    lj[i].first_block = blocks;
+    blocks += in[i].L / lj[i].S;
+    count[i] = in[i].L / lj[i].S;
+  }
+  plan->leaf_off = used;
+  plan->leaf_blocks = blocks;
+  plan->njobs = njobs;
+  used += sizeof(RefitJob) * njobs;
+  // upper levels: each pass reduces up to 8 more levels of every tree that
+  // still has more than one node at its current level
+  for (;;) {
+    uint32_t act = 0;
+    for (uint32_t i = 0; i < njobs; ++i) act += count[i] > 1 ? 1u : 0u;
+    if (act == 0) break;
+    if (plan->npasses >= kMaxRefitPasses || !need(sizeof(ReduceJob) * act)) return 0;
+    ReduceJob* rj = (ReduceJob*)(out + used);
+    uint32_t k = 0, rb = 0;
+    for (uint32_t i = 0; i < njobs; ++i) {
+      if (count[i] <= 1) continue;
+      uint32_t S2 = count[i] < (uint32_t)kRefitThreads ? count[i] : (uint32_t)kRefitThreads;
+      rj[k].boxes = in[i].boxes;
+      rj[k].first = count[i];
+      rj[k].S = S2;
+      rj[k].first_block = rb;
+      rb += count[i] / S2;
+      count[i] /= S2;
+      ++k;
+    }
+    plan->pass_off[plan->npasses] = used;
+    plan->pass_jobs[plan->npasses] = k;
+    plan->pass_blocks[plan->npasses] = rb;
+    plan->npasses++;
+    used += sizeof(ReduceJob) * k;
+  }
+  return used;
+}
+
+hipError_t launch_refit_batch(const RefitPlan& plan, const void* dev, hipStream_t s) {
+  const char* d = (const char*)dev;
+  k_refit_leaves_batch<<<plan.leaf_blocks, kRefitThreads, 0, s>>>((const RefitJob*)(d + plan.leaf_off),
+                                                                   plan.njobs);
+  for (uint32_t p = 0; p < plan.npasses; ++p)
+    k_reduce_batch<<<plan.pass_blocks[p], kRefitThreads, 0, s>>>((const ReduceJob*)(d + plan.pass_off[p]),
+                                                                 plan.pass_jobs[p]);
+  return hipGetLastError();
 }
 
 hipError_t launch_refit(const float* tris, uint32_t n, uint32_t L, const Xf32& T, float* boxes, hipStream_t s) {

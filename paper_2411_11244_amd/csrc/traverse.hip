@@ -40,8 +40,10 @@
 
 namespace gd {
 
-constexpr int kTravThreads = 256;
+constexpr int kTravThreads = 256;                 // helper kernels
 constexpr int kWavesPerBlock = kTravThreads / kWave;
+constexpr int kTravBlock = 768;                   // k_traverse: one 12-wave workgroup per CU
+constexpr int kTravWaves = kTravBlock / kWave;
 constexpr uint32_t kQueue = 320;  // per-wave LDS queue of triangle pairs (63 + 4 x 64)
 constexpr int kRows = 4;          // expansion rows per wave iteration
 
@@ -328,7 +330,7 @@ constexpr uint32_t kLdsSlots = 512;
 struct BlockState {
   uint32_t fpre[kMaxBlocks + 1];   // prefix of the current front's segment counts
   uint32_t lpre[kMaxBlocks + 1];   // same for the leaf-pair buffer
-  uint32_t scan[kTravThreads];
+  uint32_t scan[kTravBlock];
   uint32_t fo, lo;                 // this workgroup's appends in the current round
   uint32_t best[kLdsSlots];        // per-slot running bound (float bits), refreshed each round
   float delta[kLdsSlots];
@@ -373,7 +375,7 @@ __device__ __forceinline__ uint32_t seg_addr(const uint32_t* pre, uint32_t nb, u
   return lo * seg + (e - pre[lo]);
 }
 
-// Exclusive prefix over nb <= 4 * kTravThreads counts; pre[nb] = total.
+// Exclusive prefix over nb <= 4 * kTravBlock counts; pre[nb] = total.
 __device__ __forceinline__ void block_prefix(const uint32_t* cnt, uint32_t nb, uint32_t* pre, uint32_t* tmp) {
   const uint32_t t = threadIdx.x;
   uint32_t v[4], s = 0;
@@ -385,7 +387,7 @@ __device__ __forceinline__ void block_prefix(const uint32_t* cnt, uint32_t nb, u
   }
   tmp[t] = s;
   __syncthreads();
-  for (uint32_t off = 1; off < kTravThreads; off <<= 1) {
+  for (uint32_t off = 1; off < kTravBlock; off <<= 1) {
     uint32_t x = t >= off ? tmp[t - off] : 0u;
     __syncthreads();
     tmp[t] += x;
@@ -398,7 +400,7 @@ __device__ __forceinline__ void block_prefix(const uint32_t* cnt, uint32_t nb, u
     if (idx < nb) pre[idx] = run;
     run += v[i];
   }
-  if (t == kTravThreads - 1) pre[nb] = tmp[t];
+  if (t == kTravBlock - 1) pre[nb] = tmp[t];
   __syncthreads();
 }
 
@@ -603,17 +605,17 @@ __device__ __forceinline__ void world_tri(const float* tris, uint32_t pos, const
   }
 }
 
-__global__ __launch_bounds__(kTravThreads) void k_traverse(TravParams p) {
+__global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   __shared__ BlockState bs_;
-  __shared__ uint4 sq[kWavesPerBlock][kQueue];
+  __shared__ uint4 sq[kTravWaves][kQueue];
   BlockState* bs = &bs_;
   Ctl* c = p.ctl;
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint32_t wib = tid >> 6;
-  const uint64_t gw = (uint64_t)blockIdx.x * kWavesPerBlock + wib;
-  const uint64_t nw = (uint64_t)gridDim.x * kWavesPerBlock;
+  const uint64_t gw = (uint64_t)blockIdx.x * kTravWaves + wib;
+  const uint64_t nw = (uint64_t)gridDim.x * kTravWaves;
   uint4* q = sq[wib];
   const bool lds_slots = p.n_slots <= kLdsSlots;
   if (tid < ST_N) bs->stats[tid] = 0ull;
@@ -622,7 +624,7 @@ __global__ __launch_bounds__(kTravThreads) void k_traverse(TravParams p) {
     bs->lo = 0u;
   }
   if (lds_slots)
-    for (uint32_t s = tid; s < p.n_slots; s += kTravThreads) bs->delta[s] = p.st[s].delta;
+    for (uint32_t s = tid; s < p.n_slots; s += kTravBlock) bs->delta[s] = p.st[s].delta;
 
   for (uint32_t round = 0;; ++round) {
     if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) break;
@@ -636,7 +638,7 @@ __global__ __launch_bounds__(kTravThreads) void k_traverse(TravParams p) {
     rd.lin = p.leaf[round & 1u];
     rd.lout = p.leaf[(round + 1u) & 1u];
     if (lds_slots)
-      for (uint32_t s = tid; s < p.n_slots; s += kTravThreads) bs->best[s] = ld_rlx(&p.st[s].best);
+      for (uint32_t s = tid; s < p.n_slots; s += kTravBlock) bs->best[s] = ld_rlx(&p.st[s].best);
     block_prefix(p.fcount[round & 1u], rd.nb, bs->fpre, bs->scan);
     block_prefix(p.lcount[round & 1u], rd.nb, bs->lpre, bs->scan);
     const uint32_t n = bs->fpre[rd.nb];
@@ -813,7 +815,7 @@ hipError_t launch_init(const TravParams& p, hipStream_t s) {
 
 hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, uint32_t* threads) {
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_traverse, kTravThreads, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_traverse, kTravBlock, 0);
   if (e != hipSuccess) return e;
   hipDeviceProp_t prop;
   e = hipGetDeviceProperties(&prop, device);
@@ -824,7 +826,7 @@ hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, u
   uint32_t total = b * (uint32_t)prop.multiProcessorCount;
   if (total > kMaxBlocks) total = kMaxBlocks;   // the per-round prefix lives in LDS
   *blocks = total;
-  *threads = kTravThreads;
+  *threads = kTravBlock;
   return hipSuccess;
 }
 
