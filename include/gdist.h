@@ -123,6 +123,8 @@ typedef struct {
   double ms_refit;          /* device time of the refit kernels (HIP events)       */
   double ms_traversal;      /* device time of the traversal + re-eval kernel       */
   double ms_total;          /* device time of the whole query (refit to result)    */
+  double ms_traverse_kernel;/* summed device time of the k_traverse launches alone   */
+  uint64_t traverse_launches;/* k_traverse launches (groups and capacity retries)     */
 } gdist_stats_t;
 
 /* ---------------------------------------------------------------- context */

@@ -56,7 +56,7 @@ struct Mesh {
 struct gdist_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   std::unordered_map<uint64_t, Mesh*> meshes;
   uint64_t next_handle = 1;
   // tunables
@@ -244,12 +244,18 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
     HIPCHK(launch_init(p, c->stream));
     if (*first_launch) HIPCHK(hipEventRecord(c->ev[2], c->stream));
     *first_launch = false;
+    HIPCHK(hipEventRecord(c->ev[4], c->stream));
     HIPCHK(launch_traverse(p, c->trav_blocks, c->trav_threads, c->stream));
+    HIPCHK(hipEventRecord(c->ev[5], c->stream));
     HIPCHK(launch_reeval(p, reeval_blocks(gn), c->stream));
     HIPCHK(hipEventRecord(c->ev[3], c->stream));
     HIPCHK(hipMemcpyAsync(&hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(out, p.res, sizeof(gdist_result_t) * gn, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    float kms = 0.f;
+    HIPCHK(hipEventElapsedTime(&kms, c->ev[4], c->ev[5]));
+    c->last.ms_traverse_kernel += kms;
+    c->last.traverse_launches += 1;
     if (hctl.abort) return fail(GDIST_E_DEVICE, "traversal grid barrier timed out");
     if (!hctl.overflow) {
       // keep grown capacities for the next queries on this context
@@ -461,7 +467,7 @@ gdist_status_t gdist_create(int device, gdist_ctx_t* out) {
     delete c;
     return fail(GDIST_E_DEVICE, "hipStreamCreate failed");
   }
-  for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&c->ev[i]));
+  for (int i = 0; i < 6; ++i) HIPCHK(hipEventCreate(&c->ev[i]));
   (void)hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, device);
   const char* tr = getenv("GDIST_TRACE");
   c->trace = tr && tr[0] && tr[0] != '0';
@@ -490,7 +496,7 @@ gdist_status_t gdist_destroy(gdist_ctx_t c) {
   DevBuf* bufs[] = {&c->refit_tab, &c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->counts, &c->cand,
                     &c->cand64, &c->ctl, &c->desc, &c->st, &c->res};
   for (DevBuf* b : bufs) release_buf(c, *b);
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 6; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;

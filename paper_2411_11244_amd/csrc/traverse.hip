@@ -137,9 +137,12 @@ __device__ __forceinline__ void append(bool take, const E& e, E* buf, uint32_t* 
   }
 }
 
-__device__ __forceinline__ void add_stat(unsigned long long* s, int idx, bool pred, uint32_t lane) {
-  uint64_t m = __ballot(pred);
-  if (lane == 0 && m) atomicAdd(&s[idx], (unsigned long long)__popcll(m));
+// Per-wave counters (wave-uniform values), flushed to LDS once per kernel.
+struct WaveStats {
+  uint32_t v[ST_N];
+};
+__device__ __forceinline__ void add_stat(WaveStats& ws, int idx, bool pred) {
+  ws.v[idx] += (uint32_t)__popcll(__ballot(pred));
 }
 
 __device__ __forceinline__ uint32_t level_of(uint32_t node) { return 31u - (uint32_t)__clz(node); }
@@ -364,15 +367,24 @@ __device__ __forceinline__ void improve_best(const TravParams& p, BlockState* bs
   }
 }
 
-// Largest segment s with pre[s] <= e; the entry's address is s*seg + e - pre[s].
-__device__ __forceinline__ uint32_t seg_addr(const uint32_t* pre, uint32_t nb, uint32_t seg, uint32_t e) {
+// Largest segment s with pre[s] <= e (binary search; called with a
+// wave-uniform e, so every lane reads the same LDS words).
+__device__ __forceinline__ uint32_t seg_find(const uint32_t* pre, uint32_t nb, uint32_t e) {
   uint32_t lo = 0, hi = nb;
   while (hi - lo > 1u) {
     uint32_t mid = (lo + hi) >> 1;
     if (pre[mid] <= e) lo = mid;
     else hi = mid;
   }
-  return lo * seg + (e - pre[lo]);
+  return lo;
+}
+// Address s*seg + e - pre[s] of entry e >= pre[s0], stepping forward from the
+// segment s0 of the row's first entry (a row rarely crosses a segment end).
+__device__ __forceinline__ uint32_t seg_addr_from(const uint32_t* pre, uint32_t nb, uint32_t seg, uint32_t s0,
+                                                  uint32_t e) {
+  uint32_t s = s0;
+  while (s + 1u < nb && pre[s + 1u] <= e) ++s;
+  return s * seg + (e - pre[s]);
 }
 
 // Exclusive prefix over nb <= 4 * kTravBlock counts; pre[nb] = total.
@@ -439,8 +451,9 @@ __device__ __forceinline__ void append_rows(const bool* take, const uint4* e, ui
 // (items it0 + 64 r + lane).  All loads of the R rows are issued before any
 // result is needed, and the survivors of the R rows are appended together.
 template <int R>
-__device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs, const Round& rd, uint64_t it0,
-                                            uint64_t n_items, uint32_t k, uint32_t lane, uint64_t lt) {
+__device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs, const Round& rd, uint64_t base0,
+                                            uint64_t n_items, uint32_t k, uint32_t lane, uint64_t lt, WaveStats& ws) {
+  const uint64_t it0 = base0 + lane;
   Ctl* c = p.ctl;
   const uint32_t kk = 2 * k;
   uint4 ent[R];
@@ -449,7 +462,11 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
   for (int r = 0; r < R; ++r) {
     const uint64_t it = it0 + 64ull * r;
     act[r] = it < n_items;
-    ent[r] = act[r] ? rd.fin[seg_addr(bs->fpre, rd.nb, rd.seg_f, (uint32_t)(it >> kk))] : make_uint4(1u, 1u, 0u, 0u);
+    // one wave-uniform search for the row's first entry, lanes step forward
+    const uint64_t rb = base0 + 64ull * r;
+    const uint32_t s0 = rb < n_items ? seg_find(bs->fpre, rd.nb, (uint32_t)(rb >> kk)) : 0u;
+    ent[r] = act[r] ? rd.fin[seg_addr_from(bs->fpre, rd.nb, rd.seg_f, s0, (uint32_t)(it >> kk))]
+                    : make_uint4(1u, 1u, 0u, 0u);
   }
   bool to_leaf[R], to_front[R];
   uint4 ne[R];
@@ -467,8 +484,8 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
     uint32_t kA, kB;
     split_levels(d->depthA - level_of(ent[r].x), d->depthB - level_of(ent[r].y), kk, kA, kB);
     a = a && (sub >> (kA + kB)) == 0u;
-    add_stat(bs->stats, ST_POPPED, a && sub == 0u, lane);
-    add_stat(bs->stats, ST_CHILD, a, lane);
+    add_stat(ws, ST_POPPED, a && sub == 0u);
+    add_stat(ws, ST_CHILD, a);
     const uint32_t ca = (ent[r].x << kA) | (sub & ((1u << kA) - 1u));
     const uint32_t cb = (ent[r].y << kB) | (sub >> kA);
     bool keep = false;
@@ -494,7 +511,7 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
     ne[r] = make_uint4(ca, cb, fbits(nkey), slot);
     to_leaf[r] = a && keep && isleaf;
     to_front[r] = a && keep && !isleaf;
-    add_stat(bs->stats, ST_PUSHED, a && keep, lane);
+    add_stat(ws, ST_PUSHED, a && keep);
     // only a value that beats the bound this lane already saw can help
     const bool helps = a && (mode == 0 ? improve < best : improve > best);
     improve_best(p, bs, rd.lds_slots, helps, slot, mode, improve, lane);
@@ -507,12 +524,14 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
 // pair's 1-2 triangles of each side once, gives each of the (up to 4)
 // triangle pairs the cheap separating-axis test, and pushes the survivors
 // onto the wave's LDS queue (at most 4 x 64 per call).
-__device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockState* bs, const Round& rd, uint64_t it,
+__device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockState* bs, const Round& rd, uint64_t base,
                                                    uint64_t n_items, uint32_t lane, uint64_t lt, uint4* q,
-                                                   uint32_t& qn) {
+                                                   uint32_t& qn, WaveStats& ws) {
+  const uint64_t it = base + lane;
   bool act = it < n_items;
   uint4 ent = make_uint4(1u, 1u, 0u, 0u);
-  if (act) ent = rd.lin[seg_addr(bs->lpre, rd.nb, rd.seg_l, (uint32_t)it)];
+  const uint32_t s0 = base < n_items ? seg_find(bs->lpre, rd.nb, (uint32_t)base) : 0u;
+  if (act) ent = rd.lin[seg_addr_from(bs->lpre, rd.nb, rd.seg_l, s0, (uint32_t)it)];
   const uint32_t slot = ent.w;
   const SlotDesc* d = p.desc + slot;
   const uint32_t mode = d->mode;
@@ -520,7 +539,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
   const float best = get_best(p, bs, rd.lds_slots, slot);
   const float key = bitsf(ent.z);
   if (act) act = mode == 0 ? !(key - delta > best) : !(key + delta < best);
-  add_stat(bs->stats, ST_LEAF, act, lane);
+  add_stat(ws, ST_LEAF, act);
   uint32_t sa = 0, ea = 0, sb = 0, eb = 0;
   if (act) {
     leaf_range(ent.x, d->depthA, d->nA, sa, ea);
@@ -548,7 +567,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
     const bool valid = act && pa < ea && pb < eb;
     bool pass = valid;
     if (valid && mode == 0) pass = sep_lower(P[s4 & 1], Q[s4 >> 1]) - delta <= best;
-    add_stat(bs->stats, ST_TRI, valid, lane);
+    add_stat(ws, ST_TRI, valid);
     uint64_t m = __ballot(pass);
     if (pass) q[qn + (uint32_t)__popcll(m & lt)] = make_uint4(slot, pa, pb, 0u);
     qn += (uint32_t)__popcll(m);
@@ -558,7 +577,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
 
 // Narrow phase, stage 2: exact FP32 triangle-triangle distance on queued pairs.
 __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs, bool lds, uint4 e, bool act,
-                                            uint32_t lane, uint64_t lt) {
+                                            uint32_t lane, uint64_t lt, WaveStats& ws) {
   Ctl* c = p.ctl;
   const uint32_t slot = e.x, pa = e.y, pb = e.z;
   const SlotDesc* d = p.desc + slot;
@@ -580,14 +599,14 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
       cand = dd + delta >= best;
     }
   }
-  add_stat(bs->stats, ST_FULL, act, lane);
+  add_stat(ws, ST_FULL, act);
   Cand ce;
   ce.d32 = dd;
   ce.slot = slot;
   ce.ia = pa;
   ce.ib = pb;
   append(act && cand, ce, p.cand, &c->cand_len, p.cand_cap, &c->overflow, 4u, lane, lt);
-  add_stat(bs->stats, ST_CAND, act && cand, lane);
+  add_stat(ws, ST_CAND, act && cand);
   improve_best(p, bs, lds, act, slot, mode, improve, lane);
   improve_bound(&p.st[0].best32, sizeof(SlotState) / 4, act, slot, mode, dd, lane);
 }
@@ -618,6 +637,9 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   const uint64_t nw = (uint64_t)gridDim.x * kTravWaves;
   uint4* q = sq[wib];
   const bool lds_slots = p.n_slots <= kLdsSlots;
+  WaveStats ws;
+#pragma unroll
+  for (int i = 0; i < ST_N; ++i) ws.v[i] = 0u;
   if (tid < ST_N) bs->stats[tid] = 0ull;
   if (tid == 0) {
     bs->fo = 0u;
@@ -664,8 +686,8 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     for (uint64_t w = gw;;) {
       const bool more = w < total;
       if (more) {
-        if (w < leaf_waves) narrow_filter_wave(p, bs, rd, w * 64ull + lane, leaf_items, lane, lt, q, qn);
-        else expand_rows<kRows>(p, bs, rd, (w - leaf_waves) * 64ull * kRows + lane, exp_items, k, lane, lt);
+        if (w < leaf_waves) narrow_filter_wave(p, bs, rd, w * 64ull, leaf_items, lane, lt, q, qn, ws);
+        else expand_rows<kRows>(p, bs, rd, (w - leaf_waves) * 64ull * kRows, exp_items, k, lane, lt, ws);
         w += nw;
       }
       while (qn >= 64u || (!more && qn > 0u)) {
@@ -674,7 +696,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
         const bool a = lane < take;
         const uint4 e = q[qn + (a ? lane : 0u)];
         __builtin_amdgcn_wave_barrier();
-        narrow_full(p, bs, lds_slots, e, a, lane, lt);
+        narrow_full(p, bs, lds_slots, e, a, lane, lt, ws);
       }
       if (!more) break;
     }
@@ -689,6 +711,9 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     grid_sync(c, p.spin_limit);
   }
   if (blockIdx.x == 0 && tid == 0) c->trace_end = (unsigned long long)wall_clock64();
+  if (lane == 0)
+    for (int i = 0; i < ST_N; ++i)
+      if (i != ST_ROUNDS && i != ST_PEAK && ws.v[i]) atomicAdd(&bs->stats[i], (unsigned long long)ws.v[i]);
 
   __syncthreads();
   if (tid < ST_N && bs->stats[tid]) {
