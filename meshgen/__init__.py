@@ -359,36 +359,47 @@ def rings(frames: int = 100, nu: int = TORUS_RINGS["nu"], nv: int = TORUS_RINGS[
     return Workload("rings", [m], qs, {"gap_smooth": 0.7 - 2 * r})
 
 
+def batched_pair(seed: int, p: int, t_min: float = 1e3, t_max: float = 5e5, gap_min: float = 1e-3,
+                 gap_max: float = 1.0):
+    """Pair p of the batched workload, drawn from its own stream
+    default_rng([seed, p]) so any pair can be generated alone.
+    Returns (mesh_a, mesh_b, pose_a, pose_b, gap)."""
+    rng = np.random.default_rng([seed, p])
+    ta = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
+    tb = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
+    ma = random_mesh_of_size(rng, ta)
+    mb = random_mesh_of_size(rng, tb)
+    ra, rb = random_rotation(rng), random_rotation(rng)
+    g = math.exp(rng.uniform(math.log(gap_min), math.log(gap_max)))
+    pa, pb = place_with_gap(rng, ma, mb, g, ra, rb)
+    return ma, mb, pa, pb, g
+
+
 def batched(seed: int = 1, n_pairs: int = 256, t_min: float = 1e3, t_max: float = 5e5,
             gap_min: float = 1e-3, gap_max: float = 1.0) -> Workload:
     """n_pairs independent mesh pairs with log-uniform sizes, random SO(3)
     poses and a support-function gap g (log-uniform), so each distance >= g."""
-    rng = np.random.default_rng(seed)
     meshes: List[Mesh] = []
     qs: List[Query] = []
     gaps = []
     for p in range(n_pairs):
-        ta = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
-        tb = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
-        ma = random_mesh_of_size(rng, ta)
-        mb = random_mesh_of_size(rng, tb)
-        ra, rb = random_rotation(rng), random_rotation(rng)
-        g = math.exp(rng.uniform(math.log(gap_min), math.log(gap_max)))
-        pa, pb = place_with_gap(rng, ma, mb, g, ra, rb)
+        ma, mb, pa, pb, g = batched_pair(seed, p, t_min, t_max, gap_min, gap_max)
         meshes += [ma, mb]
         qs.append(Query(2 * p, 2 * p + 1, pa, pb, 0))
         gaps.append(g)
     return Workload("batched", meshes, qs, {"gaps": gaps})
 
 
+def serving_mesh(seed: int, i: int, t_min: float = 1e4, t_max: float = 2e6) -> Mesh:
+    """Mesh i of the serving pool, from its own stream default_rng([seed, i])."""
+    rng = np.random.default_rng([seed, i])
+    t = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
+    return random_mesh_of_size(rng, t)
+
+
 def serving_pool(seed: int = 2, n_meshes: int = 64, t_min: float = 1e4,
                  t_max: float = 2e6) -> List[Mesh]:
-    rng = np.random.default_rng(seed)
-    out = []
-    for _ in range(n_meshes):
-        t = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
-        out.append(random_mesh_of_size(rng, t))
-    return out
+    return [serving_mesh(seed, i, t_min, t_max) for i in range(n_meshes)]
 
 
 def serving_stream(pool: List[Mesh], rate: float, n_queries: int, seed: int = 3,

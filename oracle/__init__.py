@@ -14,7 +14,8 @@ intersection (distance zero on penetration, Sec. 7).
 Reported pair (a reading of the paper, which does not say which pair to
 report): the tie set is every triangle pair whose distance lies within
 ``tau = 1e-12 * max(1, M)`` of the optimum, with M the largest world
-coordinate magnitude of either posed mesh; the canonical pair is the
+coordinate magnitude over the corners of either mesh's local bounding box
+under its pose; the canonical pair is the
 lexicographically smallest (tri_a, tri_b) of the tie set.
 """
 from __future__ import annotations
@@ -82,6 +83,8 @@ def _load():
     lib.orc_bvh.argtypes = q + [C.POINTER(OrcResult), i64p, i64]
     lib.orc_max_vertex_pairs.restype = C.c_double
     lib.orc_max_vertex_pairs.argtypes = [fp, i64, dp, fp, i64, dp, C.c_int]
+    lib.orc_vertex_row_max.restype = None
+    lib.orc_vertex_row_max.argtypes = [fp, i64, dp, fp, i64, dp, C.c_int, dp]
     _lib = lib
     return lib
 
@@ -157,10 +160,22 @@ def pose_points(verts, pose12):
 
 
 # ---------------------------------------------------------------- queries
-def tau_for(verts_a, pose_a12, verts_b, pose_b12) -> float:
-    """Tie tolerance 1e-12 * max(1, M), M = largest world coordinate magnitude."""
-    m = max(float(np.max(np.abs(pose_points(verts_a, pose_a12)))),
-            float(np.max(np.abs(pose_points(verts_b, pose_b12)))))
+def tau_for(verts_a, tris_a, pose_a12, verts_b, tris_b, pose_b12) -> float:
+    """Tie tolerance 1e-12 * max(1, M).  M is the largest world coordinate
+    magnitude over the eight corners of each mesh's local bounding box (the
+    box of the vertices its triangles use), posed in FP64."""
+    def extent(v, f, p):
+        fi = np.asarray(f, dtype=np.int64).ravel()
+        if fi.size == 0 or fi.min() < 0 or fi.max() >= v.shape[0]:
+            raise ValueError("triangle vertex index out of range (or no triangles)")
+        used = np.zeros(v.shape[0], dtype=bool)
+        used[fi] = True
+        u = v[used].astype(np.float64)
+        lo, hi = u.min(axis=0), u.max(axis=0)
+        corners = np.array([[hi[k] if (c >> k) & 1 else lo[k] for k in range(3)] for c in range(8)])
+        p = np.asarray(p, dtype=np.float64).reshape(12)
+        return float(np.abs(corners @ p[:9].reshape(3, 3).T + p[9:]).max())
+    m = max(extent(verts_a, tris_a, pose_a12), extent(verts_b, tris_b, pose_b12))
     return 1e-12 * max(1.0, m)
 
 
@@ -179,7 +194,7 @@ def query(verts_a, tris_a, pose_a12, verts_b, tris_b, pose_b12, mode: int = 0,
     fb = np.ascontiguousarray(tris_b, dtype=np.uint32)
     pa, pb = _d(pose_a12).reshape(12), _d(pose_b12).reshape(12)
     if tau is None:
-        tau = tau_for(va, pa, vb, pb)
+        tau = tau_for(va, fa, pa, vb, fb, pb)
     if method == "auto":
         method = "brute" if fa.shape[0] * fb.shape[0] <= 8_000_000 else "bvh"
     if threads is None:
@@ -216,3 +231,49 @@ def max_vertex_pairs(verts_a, pose_a12, verts_b, pose_b12, threads: int = 8) -> 
     return float(lib.orc_max_vertex_pairs(_ptr(va, C.c_float), va.shape[0], _ptr(pa, C.c_double),
                                           _ptr(vb, C.c_float), vb.shape[0], _ptr(pb, C.c_double),
                                           int(threads)))
+
+
+def vertex_row_max(verts_a, pose_a12, verts_b, pose_b12, threads: int = 8) -> np.ndarray:
+    """rowmax[i] = max over vertices b of |a_i - b| after the poses (FP64)."""
+    lib = _load()
+    va = np.ascontiguousarray(verts_a, dtype=np.float32)
+    vb = np.ascontiguousarray(verts_b, dtype=np.float32)
+    pa, pb = _d(pose_a12).reshape(12), _d(pose_b12).reshape(12)
+    out = np.zeros(va.shape[0])
+    lib.orc_vertex_row_max(_ptr(va, C.c_float), va.shape[0], _ptr(pa, C.c_double),
+                           _ptr(vb, C.c_float), vb.shape[0], _ptr(pb, C.c_double), int(threads),
+                           _ptr(out, C.c_double))
+    return out
+
+
+def max_by_vertices(verts_a, tris_a, pose_a12, verts_b, tris_b, pose_b12, threads: int = 8,
+                    tau: Optional[float] = None) -> dict:
+    """D_max and its tie set from the vertex-pair definition (the maximum over
+    two closed triangles is attained at vertices, so the triangle pairs tied
+    at D_max are the pairs of triangles incident to the tied vertex pairs).
+    Exact for the value; the tie set is complete for pairs within tau."""
+    va = np.ascontiguousarray(verts_a, dtype=np.float32)
+    vb = np.ascontiguousarray(verts_b, dtype=np.float32)
+    fa = np.ascontiguousarray(tris_a, dtype=np.uint32)
+    fb = np.ascontiguousarray(tris_b, dtype=np.uint32)
+    if tau is None:
+        tau = tau_for(va, fa, pose_a12, vb, fb, pose_b12)
+    rm = vertex_row_max(va, pose_a12, vb, pose_b12, threads)
+    D = float(rm.max())
+    A = pose_points(va, pose_a12)
+    B = pose_points(vb, pose_b12)
+    tied_pairs = []
+    for i in np.nonzero(rm >= D - tau)[0]:
+        d = np.sqrt(((B - A[i]) ** 2).sum(1))
+        for j in np.nonzero(d >= D - tau)[0]:
+            tied_pairs.append((int(i), int(j)))
+    tri_pairs = set()
+    for i, j in tied_pairs:
+        ta = np.nonzero((fa == i).any(1))[0]
+        tb = np.nonzero((fb == j).any(1))[0]
+        for x in ta:
+            for y in tb:
+                tri_pairs.add((int(x), int(y)))
+    ties = sorted(tri_pairs)
+    return {"distance": D, "tri_a": ties[0][0], "tri_b": ties[0][1], "n_ties": len(ties),
+            "ties": np.array(ties, dtype=np.int64), "tau": float(tau), "method": "vertex-pairs"}

@@ -676,13 +676,16 @@ static void* vp_worker(void* arg) {
     int64_t a0 = __sync_fetch_and_add(j->next, 64);
     if (a0 >= j->na) break;
     int64_t a1 = a0 + 64 < j->na ? a0 + 64 : j->na;
+    /* squared distances compare like distances; one square root at the end */
     for (int64_t a = a0; a < a1; ++a)
       for (int64_t b = 0; b < j->nb; ++b) {
-        double d = vdist(j->pa + 3 * a, j->pb + 3 * b);
-        if (d > best) best = d;
+        double e[3];
+        vsub(j->pa + 3 * a, j->pb + 3 * b, e);
+        double d2 = vdot(e, e);
+        if (d2 > best) best = d2;
       }
   }
-  j->best = best;
+  j->best = best < 0.0 ? best : sqrt(best);
   return NULL;
 }
 
@@ -705,4 +708,51 @@ double orc_max_vertex_pairs(const float* va, int64_t nva, const double pose_a[12
   }
   free(jobs); free(th); free(pa); free(pb);
   return best;
+}
+
+/* ------------------------------------------------------------------ */
+/* per-vertex farthest distance (rows of the vertex-pair maximum)      */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  const double *pa, *pb;
+  int64_t na, nb;
+  int64_t* next;
+  double* rowmax;
+} rm_job;
+
+static void* rm_worker(void* arg) {
+  rm_job* j = (rm_job*)arg;
+  for (;;) {
+    int64_t a0 = __sync_fetch_and_add(j->next, 64);
+    if (a0 >= j->na) break;
+    int64_t a1 = a0 + 64 < j->na ? a0 + 64 : j->na;
+    for (int64_t a = a0; a < a1; ++a) {
+      double best = -1.0;
+      for (int64_t b = 0; b < j->nb; ++b) {
+        double e[3];
+        vsub(j->pa + 3 * a, j->pb + 3 * b, e);
+        double d2 = vdot(e, e);
+        if (d2 > best) best = d2;
+      }
+      j->rowmax[a] = sqrt(best);
+    }
+  }
+  return NULL;
+}
+
+void orc_vertex_row_max(const float* va, int64_t nva, const double pose_a[12],
+                        const float* vb, int64_t nvb, const double pose_b[12], int threads, double* rowmax) {
+  if (threads < 1) threads = 1;
+  double* pa = pose_all(va, nva, pose_a);
+  double* pb = pose_all(vb, nvb, pose_b);
+  rm_job* jobs = (rm_job*)calloc((size_t)threads, sizeof(rm_job));
+  pthread_t* th = (pthread_t*)calloc((size_t)threads, sizeof(pthread_t));
+  int64_t next = 0;
+  for (int i = 0; i < threads; ++i) {
+    jobs[i].pa = pa; jobs[i].pb = pb; jobs[i].na = nva; jobs[i].nb = nvb; jobs[i].next = &next;
+    jobs[i].rowmax = rowmax;
+    pthread_create(&th[i], NULL, rm_worker, &jobs[i]);
+  }
+  for (int i = 0; i < threads; ++i) pthread_join(th[i], NULL);
+  free(jobs); free(th); free(pa); free(pb);
 }

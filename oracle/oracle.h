@@ -89,6 +89,10 @@ int orc_bvh(const float* va, int64_t nva, const uint32_t* fa, int64_t nfa, const
 double orc_max_vertex_pairs(const float* va, int64_t nva, const double pose_a[12],
                             const float* vb, int64_t nvb, const double pose_b[12], int threads);
 
+/* rowmax[i] = max over vertices b of B of |a_i - b| (posed), for every vertex a_i of A. */
+void orc_vertex_row_max(const float* va, int64_t nva, const double pose_a[12],
+                        const float* vb, int64_t nvb, const double pose_b[12], int threads, double* rowmax);
+
 #ifdef __cplusplus
 }
 #endif

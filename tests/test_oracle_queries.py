@@ -137,6 +137,46 @@ def test_max_mode_equals_vertex_pairs(orc, seed):
     assert (r["tri_a"], r["tri_b"]) == (rv["tri_a"], rv["tri_b"])
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_vertex_row_max_brute(orc, seed):
+    """Each row maximum equals the plain maximum over all posed vertex pairs."""
+    rng = np.random.default_rng(50 + seed)
+    va = rng.normal(size=(97, 3)).astype(np.float32)
+    vb = rng.normal(size=(61, 3)).astype(np.float32)
+    pa = flat((g.random_rotation(rng), rng.normal(size=3)))
+    pb = flat((g.random_rotation(rng), rng.normal(size=3)))
+    rm = orc.vertex_row_max(va, pa, vb, pb, threads=3)
+    A, B = orc.pose_points(va, pa), orc.pose_points(vb, pb)
+    ref = np.sqrt(((A[:, None, :] - B[None, :, :]) ** 2).sum(-1)).max(1)
+    assert np.allclose(rm, ref, rtol=1e-15, atol=0)
+    assert rm.max() == orc.max_vertex_pairs(va, pa, vb, pb)
+
+
+@pytest.mark.parametrize("case", ["hard", "soup"])
+def test_max_by_vertices_matches_brute(orc, case):
+    """The vertex-pair route to D_max (value and tie set) agrees with brute
+    force over all triangle pairs, on the concentric-spheres geometry (every
+    tied vertex pair ties all its incident triangle pairs) and on a soup."""
+    if case == "hard":
+        w = g.hard(seed=4, n=6)
+        A, B = w.meshes
+        q = w.queries[1]
+        pa, pb = q.pose_a, q.pose_b
+    else:
+        rng = np.random.default_rng(9)
+        A, B = g.random_soup(rng, 200), g.random_soup(rng, 150)
+        pa, pb = (g.random_rotation(rng), np.zeros(3)), (g.random_rotation(rng), rng.normal(size=3))
+    r = run(orc, A, pa, B, pb, 1, "brute")
+    v = orc.max_by_vertices(A.verts, A.tris, flat(pa), B.verts, B.tris, flat(pb), threads=2)
+    assert v["distance"] == pytest.approx(r["distance"], rel=1e-15, abs=0)
+    assert v["tau"] == r["tau"]
+    assert (v["tri_a"], v["tri_b"]) == (r["tri_a"], r["tri_b"])
+    assert v["n_ties"] == r["n_ties"]
+    assert sorted(map(tuple, v["ties"].tolist())) == sorted(map(tuple, r["ties"][:r["n_ties"]].tolist()))
+    if case == "hard":
+        assert r["n_ties"] >= 25
+
+
 def _random_pair(rng, kind):
     if kind == "soup":
         return g.random_soup(rng, 400, 1.0, 0.15), g.random_soup(rng, 350, 1.0, 0.15)
