@@ -194,6 +194,65 @@ gdist_status_t gdist_query_batch(gdist_ctx_t ctx, uint32_t n, const gdist_query_
 /* Counters of the most recent query call on this context. */
 gdist_status_t gdist_last_stats(gdist_ctx_t ctx, gdist_stats_t* out);
 
+/* ----------------------------------------------------------------- serving */
+/* Continuous batching (not in the paper; it serves queries of different
+ * sizes as they arrive).  A worker thread owns the context's stream and runs
+ * device steps of a few traversal rounds over all queries in flight.  Between
+ * steps it admits queued queries into free slots while the shared traversal
+ * storage has room, and it completes every query whose traversal has drained:
+ * FP64 re-evaluation, then the result is queued for gdist_server_poll.  A
+ * query's result equals what gdist_query returns for it alone.  While a
+ * server runs, other query calls on its context return GDIST_E_BUSY. */
+typedef struct gdist_server* gdist_server_t;
+
+typedef struct {
+  uint32_t max_slots;       /* queries in flight, 1..512 (0 = 64)                        */
+  uint32_t rounds_per_step; /* traversal rounds per device step (0 = 4)                  */
+  uint64_t front_capacity;  /* entries per front and per leaf-pair buffer (0 = 2^25, at
+                               most 2^28); doubles when one query overflows it alone     */
+  uint32_t cand_per_slot;   /* FP64 candidates per query (0 = 2^17, at most 2^26); a
+                               query that needs more fails with GDIST_E_CAPACITY        */
+  uint32_t max_tris;        /* largest mesh a query refits, i.e. the smaller mesh of
+                               its pair (0 = largest mesh built on the context when the
+                               server starts); sizes the per-slot box storage            */
+} gdist_server_config_t;
+
+typedef struct {
+  uint64_t tag;             /* caller's tag from gdist_server_submit                      */
+  uint64_t t_submit_ns;     /* steady clock (CLOCK_MONOTONIC) at submit                   */
+  uint64_t t_done_ns;       /* steady clock when the result reached host memory           */
+  gdist_result_t result;    /* result.status != GDIST_OK for a failed query              */
+} gdist_completion_t;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, failed, requeued;
+  uint64_t steps, rounds;
+  uint32_t active, pending; /* at the time of the call                                    */
+  uint32_t concurrency;     /* current admission limit (halved after a storage overflow) */
+  uint32_t reserved;
+  double device_ms;         /* device time of all steps (HIP events)                     */
+} gdist_server_stats_t;
+
+/* Start a server on ctx (config may be NULL for defaults).  Allocates all of
+ * its device storage up front (the front buffers grow only as front_capacity
+ * says).  E_BUSY if ctx already has a server. */
+gdist_status_t gdist_server_start(gdist_ctx_t ctx, const gdist_server_config_t* config, gdist_server_t* out);
+
+/* Queue one query.  Handles, poses and mode are validated here (E_HANDLE /
+ * E_INVALID); E_CAPACITY if the smaller mesh of the pair exceeds max_tris.
+ * Thread-safe. */
+gdist_status_t gdist_server_submit(gdist_server_t srv, const gdist_query_desc_t* q, uint64_t tag);
+
+/* Move up to max finished queries into out[]; returns how many.  Thread-safe,
+ * non-blocking. */
+uint32_t gdist_server_poll(gdist_server_t srv, gdist_completion_t* out, uint32_t max);
+
+gdist_status_t gdist_server_stats(gdist_server_t srv, gdist_server_stats_t* out);
+
+/* Stop the worker (queries still queued or in flight are dropped), free the
+ * server's storage and release the context. */
+gdist_status_t gdist_server_stop(gdist_server_t srv);
+
 /* Message for the most recent failure on the calling thread ("" if none). */
 const char* gdist_last_error(void);
 

@@ -13,11 +13,11 @@
 #include <unordered_map>
 #include <vector>
 
-#include "internal.hpp"
+#include "host.hpp"
 
 using namespace gd;
 
-namespace {
+namespace gd {
 
 thread_local std::string t_err;
 
@@ -30,53 +30,6 @@ gdist_status_t fail(gdist_status_t s, const char* fmt, ...) {
   t_err = buf;
   return s;
 }
-
-#define HIPCHK(expr)                                                                              \
-  do {                                                                                            \
-    hipError_t _e = (expr);                                                                       \
-    if (_e != hipSuccess) return fail(GDIST_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e)); \
-  } while (0)
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
-
-struct Mesh {
-  uint32_t n_tris = 0, L = 0, depth = 0;
-  float* tris = nullptr;
-  uint32_t* orig = nullptr;
-  float* boxes = nullptr;
-  float root[6] = {0, 0, 0, 0, 0, 0};
-  uint64_t bytes = 0;
-};
-
-}  // namespace
-
-struct gdist_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  std::unordered_map<uint64_t, Mesh*> meshes;
-  uint64_t next_handle = 1;
-  // tunables
-  uint32_t front_cap = 1u << 24, leaf_cap = 1u << 24, cand_cap = 1u << 21;
-  uint32_t max_retries = 8, expand_budget = 1u << 18, k_cap = 5, blocks_per_cu = 0, bounds = 0;
-  double kappa = 64.0;
-  uint64_t memory_budget = 0, bytes_held = 0;
-  // workspace
-  DevBuf ws_boxes, front[2], leaf[2], counts, cand, cand64, ctl, desc, st, res, refit_tab;
-  void* pinned = nullptr;       // host staging for descriptors and job tables
-  size_t pinned_bytes = 0;
-  uint32_t trav_blocks = 0, trav_threads = 0;
-  int wall_khz = 0;
-  bool trace = false;
-  uint32_t group_hint = 0;                 // largest group of queries that fit one launch
-  unsigned long long last_ctl_sum[ST_N] = {};
-  gdist_stats_t last{};
-};
-
-namespace {
 
 gdist_status_t dalloc(gdist_ctx* c, size_t bytes, void** p) {
   if (bytes == 0) bytes = 256;
@@ -181,10 +134,6 @@ gdist_status_t refresh_grid(gdist_ctx* c) {
   return GDIST_OK;
 }
 
-// enough workgroups for the candidate lists seen in practice; the kernels are
-// grid-stride, so any count is correct
-uint32_t reeval_blocks(uint32_t n_slots) { return n_slots > 64 ? 1024u : 256u; }
-
 constexpr uint32_t kCapLimit = 1u << 28;      // entries per front / leaf buffer
 constexpr uint32_t kCandLimit = 1u << 26;     // FP64 candidates
 
@@ -200,16 +149,18 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
   const uint32_t nb = c->trav_blocks;
   // per-workgroup segments; the root pairs all start in segment 0
   auto seg_of = [&](uint32_t cap) {
-    uint32_t v = cap / nb;
-    if (v < gn) v = gn;
+    uint32_t v = cap / (nb + 1);
+    if (v < gn) v = gn;   // the admission segment takes every root pair
     return v < 1u ? 1u : v;
   };
   uint32_t sf = seg_of(c->front_cap), sl = seg_of(c->leaf_cap);
-  uint32_t ccap = c->cand_cap;
+  uint32_t cps = c->cand_cap / gn;
+  if (cps < 1024u) cps = 1024u;
   Ctl hctl;
-  if ((s = ensure(c, c->counts, 16ull * nb)) != GDIST_OK) return s;
+  if ((s = ensure(c, c->counts, 16ull * (nb + 1))) != GDIST_OK) return s;
   for (uint32_t attempt = 0;; ++attempt) {
-    const uint64_t fcap = (uint64_t)sf * nb, lcap = (uint64_t)sl * nb;
+    const uint64_t fcap = (uint64_t)sf * (nb + 1), lcap = (uint64_t)sl * (nb + 1);
+    const uint64_t ccap = (uint64_t)cps * gn;
     for (int b = 0; b < 2; ++b) {
       if ((s = ensure(c, c->front[b], 16ull * fcap)) != GDIST_OK) return s;
       if ((s = ensure(c, c->leaf[b], 16ull * lcap)) != GDIST_OK) return s;
@@ -227,27 +178,33 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
     p.leaf[1] = (uint4*)c->leaf[1].p;
     uint32_t* cnt = (uint32_t*)c->counts.p;
     p.fcount[0] = cnt;
-    p.fcount[1] = cnt + nb;
-    p.lcount[0] = cnt + 2 * nb;
-    p.lcount[1] = cnt + 3 * nb;
+    p.fcount[1] = cnt + (nb + 1);
+    p.lcount[0] = cnt + 2 * (nb + 1);
+    p.lcount[1] = cnt + 3 * (nb + 1);
     p.nblocks = nb;
     p.cand = (Cand*)c->cand.p;
     p.cand_d64 = (double*)c->cand64.p;
     p.ctl = (Ctl*)c->ctl.p;
+    p.slot_list = nullptr;
+    p.n_list = gn;
+    p.cand_per_slot = cps;
+    p.round0 = 0;
+    p.max_rounds = 0xffffffffu;
     p.seg_front = sf;
     p.seg_leaf = sl;
-    p.cand_cap = ccap;
     p.n_slots = gn;
     p.expand_budget = c->expand_budget;
     p.k_cap = c->k_cap;
     p.spin_limit = 1u << 26;
-    HIPCHK(launch_init(p, c->stream));
+    p.cand_stop = 1u;
+    HIPCHK(launch_reset(p, c->stream));
+    HIPCHK(launch_admit(p, c->stream));
     if (*first_launch) HIPCHK(hipEventRecord(c->ev[2], c->stream));
     *first_launch = false;
     HIPCHK(hipEventRecord(c->ev[4], c->stream));
     HIPCHK(launch_traverse(p, c->trav_blocks, c->trav_threads, c->stream));
     HIPCHK(hipEventRecord(c->ev[5], c->stream));
-    HIPCHK(launch_reeval(p, reeval_blocks(gn), c->stream));
+    HIPCHK(launch_reeval(p, c->stream));
     HIPCHK(hipEventRecord(c->ev[3], c->stream));
     HIPCHK(hipMemcpyAsync(&hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(out, p.res, sizeof(gdist_result_t) * gn, hipMemcpyDeviceToHost, c->stream));
@@ -261,21 +218,21 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
       // keep grown capacities for the next queries on this context
       if (fcap > c->front_cap) c->front_cap = (uint32_t)fcap;
       if (lcap > c->leaf_cap) c->leaf_cap = (uint32_t)lcap;
-      if (ccap > c->cand_cap) c->cand_cap = ccap;
+      if (ccap > c->cand_cap) c->cand_cap = (uint32_t)(ccap < kCandLimit ? ccap : kCandLimit);
       break;
     }
     const bool can_grow = ((hctl.overflow & 1u) == 0 || 2ull * fcap <= kCapLimit) &&
                           ((hctl.overflow & 2u) == 0 || 2ull * lcap <= kCapLimit) &&
-                          ((hctl.overflow & 4u) == 0 || ccap < kCandLimit);
+                          ((hctl.overflow & 4u) == 0 || 2ull * ccap <= kCandLimit);
     if (!can_grow || attempt >= c->max_retries) {
       *split = gn > 1;
-      return fail(GDIST_E_CAPACITY, "traversal storage exhausted (front %llu, leaf %llu, candidates %u entries, %u queries)",
-                  (unsigned long long)fcap, (unsigned long long)lcap, ccap, gn);
+      return fail(GDIST_E_CAPACITY, "traversal storage exhausted (front %llu, leaf %llu, candidates %llu entries, %u queries)",
+                  (unsigned long long)fcap, (unsigned long long)lcap, (unsigned long long)ccap, gn);
     }
     c->last.retries++;
     if (hctl.overflow & 1u) sf *= 2u;
     if (hctl.overflow & 2u) sl *= 2u;
-    if (hctl.overflow & 4u) ccap = ccap >= kCandLimit / 2 ? kCandLimit : ccap * 2u;
+    if (hctl.overflow & 4u) cps *= 2u;
   }
   for (int i = 0; i < ST_N; ++i) {
     if (i == ST_PEAK) c->last_ctl_sum[i] = std::max(c->last_ctl_sum[i], hctl.stats[i]);
@@ -296,8 +253,65 @@ void print_trace(gdist_ctx* c, uint32_t g0, uint32_t gn, const Ctl& h) {
   }
 }
 
+gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx, SlotDesc* dp, Mesh** Bout) {
+  Mesh* ma = find_mesh(c, q.a);
+  Mesh* mb = find_mesh(c, q.b);
+  if (!ma || !mb) return fail(GDIST_E_HANDLE, "query %u: unknown mesh handle", idx);
+  if (q.mode > 1) return fail(GDIST_E_INVALID, "query %u: unknown mode %u", idx, q.mode);
+  gdist_status_t s = check_pose(&q.pa, "a");
+  if (s != GDIST_OK) return s;
+  s = check_pose(&q.pb, "b");
+  if (s != GDIST_OK) return s;
+  // refit the smaller tree into the larger one's frame
+  bool swapped = ma->n_tris < mb->n_tris;
+  Mesh* A = swapped ? mb : ma;
+  Mesh* B = swapped ? ma : mb;
+  const gdist_pose_t& PA = swapped ? q.pb : q.pa;
+  const gdist_pose_t& PB = swapped ? q.pa : q.pb;
+  SlotDesc& d = *dp;
+  std::memset(&d, 0, sizeof(d));
+  d.boxA = A->boxes;
+  d.trisA = A->tris;
+  d.trisB = B->tris;
+  d.origA = A->orig;
+  d.origB = B->orig;
+  d.nA = A->n_tris;
+  d.nB = B->n_tris;
+  d.LA = A->L;
+  d.LB = B->L;
+  d.depthA = A->depth;
+  d.depthB = B->depth;
+  d.mode = q.mode;
+  d.enhanced = c->bounds == 0 ? 1u : 0u;
+  d.swapped = swapped ? 1u : 0u;
+  d.kappa_u = (float)(c->kappa * std::ldexp(1.0, -24));
+  // B local -> A local: R = RA^T RB, t = RA^T (tB - tA)
+  for (int r = 0; r < 3; ++r) {
+    for (int col = 0; col < 3; ++col) {
+      double s2 = 0.0;
+      for (int k = 0; k < 3; ++k) s2 += PA.R[3 * k + r] * PB.R[3 * k + col];
+      d.T.R[3 * r + col] = (float)s2;
+    }
+    double s3 = 0.0;
+    for (int k = 0; k < 3; ++k) s3 += PA.R[3 * k + r] * (PB.t[k] - PA.t[k]);
+    d.T.t[r] = (float)s3;
+  }
+  for (int k = 0; k < 9; ++k) {
+    d.RA[k] = PA.R[k];
+    d.RB[k] = PB.R[k];
+  }
+  for (int k = 0; k < 3; ++k) {
+    d.tA[k] = PA.t[k];
+    d.tB[k] = PB.t[k];
+  }
+  double M = std::fmax(world_extent(A->root, PA), world_extent(B->root, PB));
+  d.tau = 1e-12 * std::fmax(1.0, M);
+  d.err_bound = 1e-13 * std::fmax(1.0, M);
+  *Bout = B;
+  return GDIST_OK;
+}
+
 struct SlotPlan {
-  Mesh* A;
   Mesh* B;
   size_t box_off;  // float offset of B's refitted boxes in ws_boxes
 };
@@ -309,60 +323,9 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
   std::vector<SlotPlan> plan(n);
   size_t box_floats = 0;
   for (uint32_t i = 0; i < n; ++i) {
-    Mesh* ma = find_mesh(c, q[i].a);
-    Mesh* mb = find_mesh(c, q[i].b);
-    if (!ma || !mb) return fail(GDIST_E_HANDLE, "query %u: unknown mesh handle", i);
-    if (q[i].mode > 1) return fail(GDIST_E_INVALID, "query %u: unknown mode %u", i, q[i].mode);
-    gdist_status_t s = check_pose(&q[i].pa, "a");
+    Mesh* B = nullptr;
+    gdist_status_t s = make_slot(c, q[i], i, &desc[i], &B);
     if (s != GDIST_OK) return s;
-    s = check_pose(&q[i].pb, "b");
-    if (s != GDIST_OK) return s;
-    // refit the smaller tree into the larger one's frame
-    bool swapped = ma->n_tris < mb->n_tris;
-    Mesh* A = swapped ? mb : ma;
-    Mesh* B = swapped ? ma : mb;
-    const gdist_pose_t& PA = swapped ? q[i].pb : q[i].pa;
-    const gdist_pose_t& PB = swapped ? q[i].pa : q[i].pb;
-    SlotDesc& d = desc[i];
-    std::memset(&d, 0, sizeof(d));
-    d.boxA = A->boxes;
-    d.trisA = A->tris;
-    d.trisB = B->tris;
-    d.origA = A->orig;
-    d.origB = B->orig;
-    d.nA = A->n_tris;
-    d.nB = B->n_tris;
-    d.LA = A->L;
-    d.LB = B->L;
-    d.depthA = A->depth;
-    d.depthB = B->depth;
-    d.mode = q[i].mode;
-    d.enhanced = c->bounds == 0 ? 1u : 0u;
-    d.swapped = swapped ? 1u : 0u;
-    d.kappa_u = (float)(c->kappa * std::ldexp(1.0, -24));
-    // B local -> A local: R = RA^T RB, t = RA^T (tB - tA)
-    for (int r = 0; r < 3; ++r) {
-      for (int col = 0; col < 3; ++col) {
-        double s2 = 0.0;
-        for (int k = 0; k < 3; ++k) s2 += PA.R[3 * k + r] * PB.R[3 * k + col];
-        d.T.R[3 * r + col] = (float)s2;
-      }
-      double s3 = 0.0;
-      for (int k = 0; k < 3; ++k) s3 += PA.R[3 * k + r] * (PB.t[k] - PA.t[k]);
-      d.T.t[r] = (float)s3;
-    }
-    for (int k = 0; k < 9; ++k) {
-      d.RA[k] = PA.R[k];
-      d.RB[k] = PB.R[k];
-    }
-    for (int k = 0; k < 3; ++k) {
-      d.tA[k] = PA.t[k];
-      d.tB[k] = PB.t[k];
-    }
-    double M = std::fmax(world_extent(A->root, PA), world_extent(B->root, PB));
-    d.tau = 1e-12 * std::fmax(1.0, M);
-    d.err_bound = 1e-13 * std::fmax(1.0, M);
-    plan[i].A = A;
     plan[i].B = B;
     plan[i].box_off = box_floats;
     box_floats += 6ull * 2ull * B->L;
@@ -448,7 +411,7 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
   return GDIST_OK;
 }
 
-}  // namespace
+}  // namespace gd
 
 extern "C" {
 
@@ -482,6 +445,7 @@ gdist_status_t gdist_create(int device, gdist_ctx_t* out) {
 
 gdist_status_t gdist_destroy(gdist_ctx_t c) {
   if (!c) return GDIST_OK;
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& kv : c->meshes) {
@@ -505,6 +469,7 @@ gdist_status_t gdist_destroy(gdist_ctx_t c) {
 
 gdist_status_t gdist_set_option(gdist_ctx_t c, const char* key, double v) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
   if (!key) return fail(GDIST_E_INVALID, "NULL key");
   auto u32opt = [&](uint32_t* dst, double lo, double hi) -> gdist_status_t {
     if (!(v >= lo && v <= hi) || v != std::floor(v))
@@ -542,6 +507,7 @@ gdist_status_t gdist_set_option(gdist_ctx_t c, const char* key, double v) {
 gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const uint32_t* tris, uint32_t nt,
                            uint32_t flags, gdist_mesh_t* out) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
   if (!out) return fail(GDIST_E_INVALID, "NULL output handle pointer");
   *out = 0;
   if (!verts || !tris) return fail(GDIST_E_INVALID, "NULL vertex or triangle array");
@@ -644,6 +610,7 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
 
 gdist_status_t gdist_release(gdist_ctx_t c, gdist_mesh_t h) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
   Mesh* m = find_mesh(c, h);
   if (!m) return fail(GDIST_E_HANDLE, "unknown mesh handle %llu", (unsigned long long)h);
   HIPCHK(hipSetDevice(c->device));
@@ -684,6 +651,7 @@ gdist_status_t gdist_mesh_export(gdist_ctx_t c, gdist_mesh_t h, float* boxes, fl
 gdist_status_t gdist_query(gdist_ctx_t c, gdist_mesh_t a, gdist_mesh_t b, const gdist_pose_t* pa,
                            const gdist_pose_t* pb, gdist_mode_t mode, gdist_result_t* out) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
   if (!out) return fail(GDIST_E_INVALID, "NULL result pointer");
   if (!pa || !pb) return fail(GDIST_E_INVALID, "NULL pose");
   gdist_query_desc_t d;
@@ -699,6 +667,7 @@ gdist_status_t gdist_query(gdist_ctx_t c, gdist_mesh_t a, gdist_mesh_t b, const 
 
 gdist_status_t gdist_query_batch(gdist_ctx_t c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
   HIPCHK(hipSetDevice(c->device));
   return run_queries(c, n, q, out);
 }
@@ -712,6 +681,7 @@ gdist_status_t gdist_last_stats(gdist_ctx_t c, gdist_stats_t* out) {
 
 gdist_status_t gdist_eval_box_bounds(gdist_ctx_t c, uint32_t n, const float* a, const float* b, float* out) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
   if (n == 0) return GDIST_OK;
   if (!a || !b || !out) return fail(GDIST_E_INVALID, "NULL array");
   HIPCHK(hipSetDevice(c->device));
@@ -735,6 +705,7 @@ gdist_status_t gdist_eval_box_bounds(gdist_ctx_t c, uint32_t n, const float* a, 
 gdist_status_t gdist_eval_tri_tri(gdist_ctx_t c, uint32_t n, const float* p, const float* q, uint32_t mode,
                                   float* out32, double* out64) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
   if (n == 0) return GDIST_OK;
   if (!p || !q || !out32 || !out64) return fail(GDIST_E_INVALID, "NULL array");
   if (mode > 1) return fail(GDIST_E_INVALID, "unknown mode %u", mode);

@@ -1,0 +1,74 @@
+// Host-side definitions shared by the C ABI (api.cpp) and the serving core
+// (server.cpp): contexts, mesh handles, device buffers and helpers.
+#pragma once
+#include <cstdarg>
+#include <string>
+#include <unordered_map>
+
+#include "internal.hpp"
+
+struct gdist_ctx;
+
+namespace gd {
+
+gdist_status_t fail(gdist_status_t s, const char* fmt, ...);
+
+#define HIPCHK(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t _e = (expr);                                                                       \
+    if (_e != hipSuccess) return fail(GDIST_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Mesh {
+  uint32_t n_tris = 0, L = 0, depth = 0;
+  float* tris = nullptr;
+  uint32_t* orig = nullptr;
+  float* boxes = nullptr;
+  float root[6] = {0, 0, 0, 0, 0, 0};
+  uint64_t bytes = 0;
+};
+
+
+gdist_status_t dalloc(gdist_ctx* c, size_t bytes, void** p);
+void dfree(gdist_ctx* c, void* p, size_t bytes);
+gdist_status_t ensure(gdist_ctx* c, DevBuf& b, size_t bytes);
+void release_buf(gdist_ctx* c, DevBuf& b);
+gdist_status_t check_pose(const gdist_pose_t* p, const char* which);
+Mesh* find_mesh(gdist_ctx* c, gdist_mesh_t h);
+// Validate one query and fill its descriptor (all but boxB); *B receives
+// the tree that the query refits.
+gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx, SlotDesc* d, Mesh** B);
+
+}  // namespace gd
+
+struct gdist_ctx {
+  using Mesh = gd::Mesh;
+  using DevBuf = gd::DevBuf;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::unordered_map<uint64_t, Mesh*> meshes;
+  uint64_t next_handle = 1;
+  // tunables
+  uint32_t front_cap = 1u << 24, leaf_cap = 1u << 24, cand_cap = 1u << 21;
+  uint32_t max_retries = 8, expand_budget = 1u << 18, k_cap = 5, blocks_per_cu = 0, bounds = 0;
+  double kappa = 64.0;
+  uint64_t memory_budget = 0, bytes_held = 0;
+  // workspace
+  DevBuf ws_boxes, front[2], leaf[2], counts, cand, cand64, ctl, desc, st, res, refit_tab;
+  void* pinned = nullptr;       // host staging for descriptors and job tables
+  size_t pinned_bytes = 0;
+  uint32_t trav_blocks = 0, trav_threads = 0;
+  int wall_khz = 0;
+  bool trace = false;
+  uint32_t group_hint = 0;                 // largest group of queries that fit one launch
+  unsigned long long last_ctl_sum[gd::ST_N] = {};
+  gdist_stats_t last{};
+  bool busy = false;                       // a server owns the stream and workspace
+};
+

@@ -41,6 +41,8 @@ struct SlotState {
   unsigned long long key_d;  // double bits of the FP64 optimum
   unsigned long long key_pair;  // (caller tri a << 32) | caller tri b of the reported pair
   uint32_t n_admitted;       // candidates that passed the final window
+  uint32_t n_cand;           // candidates appended to this slot's region
+  uint32_t cand_overflow;    // the region filled up
   uint32_t pad;
 };
 
@@ -60,12 +62,11 @@ constexpr uint32_t kTraceRounds = 48;
 
 // Control block of one persistent traversal launch.
 struct Ctl {
-  uint32_t cand_len;
   uint32_t overflow;       // bit 0 front, bit 1 leaf pairs, bit 2 candidates
   uint32_t abort;          // a grid barrier timed out
   uint32_t bar_count;
   uint32_t bar_gen;
-  uint32_t pad;
+  uint32_t rounds_done;    // rounds completed by the latest launch
   unsigned long long stats[ST_N];
   // per-round device timestamps (constant-rate wall clock) and front sizes
   unsigned long long trace_t[kTraceRounds];
@@ -78,20 +79,25 @@ struct TravParams {
   const SlotDesc* desc;
   SlotState* st;
   gdist_result_t* res;
-  uint4* front[2];         // segmented: workgroup b owns [b * seg_front, (b+1) * seg_front)
-  uint4* leaf[2];
-  uint32_t* fcount[2];     // per-workgroup entry counts of front[i] (nblocks each)
+  uint4* front[2];         // segmented: workgroup b owns [b * seg_front, (b+1) * seg_front); segment
+  uint4* leaf[2];          //   nblocks (the last) receives the root pairs of newly admitted queries
+  uint32_t* fcount[2];     // entry count of every segment of front[i] (nblocks + 1 each)
   uint32_t* lcount[2];
-  Cand* cand;
+  Cand* cand;              // per-slot regions of cand_per_slot entries
   double* cand_d64;
   Ctl* ctl;
-  uint32_t seg_front, seg_leaf, cand_cap;
+  const uint32_t* slot_list;  // slots to admit / re-evaluate (nullptr: slots 0 .. n_list-1)
+  uint32_t n_list;
+  uint32_t seg_front, seg_leaf, cand_per_slot;
   uint32_t nblocks;        // workgroups of the traversal launch
-  uint32_t n_slots;
+  uint32_t n_slots;        // size of the slot table
   uint32_t expand_budget;
   uint32_t k_cap;
   uint32_t spin_limit;
-  uint32_t pad;
+  uint32_t round0;         // global index of the first round of this launch (buffer parity)
+  uint32_t max_rounds;     // rounds this launch may run (the serving step)
+  uint32_t cand_stop;      // 1: a candidate-region overflow also stops the launch (the caller retries
+                           //    with larger regions); 0: it only marks the slot
 };
 
 // build.hip
@@ -131,10 +137,12 @@ size_t plan_refit_batch(const RefitJob* in, uint32_t njobs, void* staging, size_
 hipError_t launch_refit_batch(const RefitPlan& plan, const void* dev, hipStream_t s);
 
 // traverse.hip
-hipError_t launch_init(const TravParams& p, hipStream_t s);
 hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, uint32_t* threads);
 hipError_t launch_traverse(const TravParams& p, uint32_t blocks, uint32_t threads, hipStream_t s);
-hipError_t launch_reeval(const TravParams& p, uint32_t blocks, hipStream_t s);
+hipError_t launch_reeval(const TravParams& p, hipStream_t s);
+hipError_t launch_reset(const TravParams& p, hipStream_t s);
+hipError_t launch_admit(const TravParams& p, hipStream_t s);
+hipError_t launch_slot_hist(const TravParams& p, uint32_t* live, hipStream_t s);
 
 // selfcheck.hip
 hipError_t launch_eval_bounds(uint32_t n, const float* a, const float* b, float* out, hipStream_t s);

@@ -1,0 +1,514 @@
+// Serving core: continuous batching of distance queries on one context.
+//
+// A worker thread repeats one device step while queries are queued or in
+// flight:
+//   1. admission: queued queries take free slots while the shared traversal
+//      storage has room (the total live front after the last step stays below
+//      a quarter of its capacity) and the adaptive concurrency limit allows;
+//      each new slot gets its descriptor, the refit of its moving tree, its
+//      error window, greedy dive and root pair (through the admission segment);
+//   2. traversal: the persistent kernel runs at most rounds_per_step rounds of
+//      every slot in flight (new slots join the running fronts);
+//   3. a per-slot histogram of the live front and leaf-pair entries;
+//   4. every slot with no live entries is complete: FP64 re-evaluation of its
+//      candidates, its result is copied back and queued for polling, and the
+//      slot is freed.
+// A front or leaf-pair overflow puts every query in flight back at the head of
+// the queue (keeping its submit time), clears the traversal storage and halves
+// the concurrency limit; when a query overflows alone the storage doubles (up
+// to 2^28 entries per buffer) before it runs again, and beyond that it fails
+// with E_CAPACITY.  A query whose candidate region fills up fails with
+// E_CAPACITY once its traversal drains; the other queries are not affected.
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "host.hpp"
+
+using namespace gd;
+
+namespace {
+
+constexpr uint64_t kServerCapLimit = 1ull << 28;  // entries per front / leaf-pair buffer
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct Pending {
+  gdist_query_desc_t q;
+  uint64_t tag;
+  uint64_t t_submit;
+};
+
+}  // namespace
+
+struct gdist_server {
+  gdist_ctx* c = nullptr;
+  gdist_server_config_t cfg{};
+  uint32_t S = 0, nb = 0, seg_f = 0, seg_l = 0, cps = 0;
+  size_t box_stride = 0;  // floats of refitted boxes per slot
+  uint32_t max_leaves = 0;
+  DevBuf desc, st, res, boxes, front[2], leaf[2], counts, cand, cand64, ctl, live, list, tab;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // slot table (worker thread only)
+  std::vector<uint8_t> active;
+  std::vector<Pending> slot_req;
+  std::vector<uint32_t> free_slots;
+  uint32_t n_active = 0, round0 = 0, concurrency = 0, clean_steps = 0;
+  uint64_t live_total = 0;
+  // shared with the API threads
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Pending> pending;
+  std::vector<gdist_completion_t> done;
+  gdist_server_stats_t stats{};
+  std::atomic<bool> stopping{false};
+  std::thread worker;
+};
+
+namespace {
+
+TravParams params(gdist_server* sv) {
+  TravParams p;
+  std::memset(&p, 0, sizeof(p));
+  gdist_ctx* c = sv->c;
+  p.desc = (const SlotDesc*)sv->desc.p;
+  p.st = (SlotState*)sv->st.p;
+  p.res = (gdist_result_t*)sv->res.p;
+  p.front[0] = (uint4*)sv->front[0].p;
+  p.front[1] = (uint4*)sv->front[1].p;
+  p.leaf[0] = (uint4*)sv->leaf[0].p;
+  p.leaf[1] = (uint4*)sv->leaf[1].p;
+  uint32_t* cnt = (uint32_t*)sv->counts.p;
+  p.fcount[0] = cnt;
+  p.fcount[1] = cnt + (sv->nb + 1);
+  p.lcount[0] = cnt + 2 * (sv->nb + 1);
+  p.lcount[1] = cnt + 3 * (sv->nb + 1);
+  p.cand = (Cand*)sv->cand.p;
+  p.cand_d64 = (double*)sv->cand64.p;
+  p.ctl = (Ctl*)sv->ctl.p;
+  p.slot_list = (const uint32_t*)sv->list.p;
+  p.seg_front = sv->seg_f;
+  p.seg_leaf = sv->seg_l;
+  p.cand_per_slot = sv->cps;
+  p.nblocks = sv->nb;
+  p.n_slots = sv->S;
+  p.expand_budget = c->expand_budget;
+  p.k_cap = c->k_cap;
+  p.spin_limit = 1u << 26;
+  p.round0 = sv->round0;
+  p.max_rounds = sv->cfg.rounds_per_step;
+  p.cand_stop = 0;
+  return p;
+}
+
+// Pinned staging: descriptors, then a slot list, then the refit job tables.
+size_t tab_offset(const gdist_server* sv) {
+  return (sizeof(SlotDesc) * sv->S + 4ull * sv->S + 255) & ~(size_t)255;
+}
+
+// Double the front and leaf-pair buffers (all queries are out of flight).
+gdist_status_t grow_storage(gdist_server* sv) {
+  gdist_ctx* c = sv->c;
+  const uint64_t fcap = (uint64_t)sv->seg_f * (sv->nb + 1);
+  if (2 * fcap > kServerCapLimit) return GDIST_E_CAPACITY;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int b = 0; b < 2; ++b) {
+    release_buf(c, sv->front[b]);
+    release_buf(c, sv->leaf[b]);
+  }
+  sv->seg_f *= 2;
+  sv->seg_l = sv->seg_f;
+  gdist_status_t s = GDIST_OK;
+  for (int b = 0; b < 2 && s == GDIST_OK; ++b) {
+    s = ensure(c, sv->front[b], 32ull * fcap);
+    if (s == GDIST_OK) s = ensure(c, sv->leaf[b], 32ull * fcap);
+  }
+  return s;
+}
+
+void complete(gdist_server* sv, uint64_t tag, uint64_t t_submit, const gdist_result_t& r) {
+  gdist_completion_t cpl;
+  std::memset(&cpl, 0, sizeof(cpl));
+  cpl.tag = tag;
+  cpl.t_submit_ns = t_submit;
+  cpl.t_done_ns = now_ns();
+  cpl.result = r;
+  std::lock_guard<std::mutex> g(sv->mu);
+  sv->done.push_back(cpl);
+  sv->stats.completed++;
+  if (r.status != GDIST_OK) sv->stats.failed++;
+}
+
+gdist_result_t failed_result(gdist_status_t s) {
+  gdist_result_t r;
+  std::memset(&r, 0, sizeof(r));
+  r.status = (uint32_t)s;
+  r.distance = __builtin_nan("");
+  return r;
+}
+
+// Reset the traversal storage (counts of the current round's buffers, control block).
+gdist_status_t reset_storage(gdist_server* sv) {
+  TravParams p = params(sv);
+  HIPCHK(launch_reset(p, sv->c->stream));
+  return GDIST_OK;
+}
+
+// Admit the queries of `reqs` into free slots (refit, dive, root pairs).
+gdist_status_t admit(gdist_server* sv, std::vector<Pending>& reqs) {
+  gdist_ctx* c = sv->c;
+  std::vector<uint32_t> slots;
+  std::vector<RefitJob> jobs;
+  char* stage = (char*)sv->pinned;
+  const size_t desc_off = 0, list_off = sizeof(SlotDesc) * sv->S, tab_off = tab_offset(sv);
+  for (Pending& rq : reqs) {
+    SlotDesc d;
+    Mesh* B = nullptr;
+    gdist_status_t s = make_slot(c, rq.q, 0, &d, &B);
+    if (s == GDIST_OK && B->L > sv->max_leaves) s = GDIST_E_CAPACITY;
+    if (s != GDIST_OK) {
+      complete(sv, rq.tag, rq.t_submit, failed_result(s));
+      continue;
+    }
+    uint32_t slot = sv->free_slots.back();
+    sv->free_slots.pop_back();
+    d.boxB = (const float*)sv->boxes.p + sv->box_stride * slot;
+    std::memcpy(stage + desc_off + sizeof(SlotDesc) * slots.size(), &d, sizeof(SlotDesc));
+    RefitJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.tris = B->tris;
+    j.boxes = (float*)d.boxB;
+    j.T = d.T;
+    j.n = B->n_tris;
+    j.L = B->L;
+    jobs.push_back(j);
+    sv->slot_req[slot] = rq;
+    sv->active[slot] = 1;
+    slots.push_back(slot);
+  }
+  if (slots.empty()) return GDIST_OK;
+  for (size_t i = 0; i < slots.size(); ++i)
+    HIPCHK(hipMemcpyAsync((SlotDesc*)sv->desc.p + slots[i], stage + desc_off + sizeof(SlotDesc) * i, sizeof(SlotDesc),
+                          hipMemcpyHostToDevice, c->stream));
+  std::memcpy(stage + list_off, slots.data(), 4 * slots.size());
+  HIPCHK(hipMemcpyAsync(sv->list.p, stage + list_off, 4 * slots.size(), hipMemcpyHostToDevice, c->stream));
+  RefitPlan plan;
+  const size_t cap = sv->pinned_bytes - tab_off;
+  const size_t bytes = plan_refit_batch(jobs.data(), (uint32_t)jobs.size(), stage + tab_off, cap, &plan);
+  if (bytes == 0 || bytes > sv->tab.bytes) return fail(GDIST_E_DEVICE, "server refit plan does not fit");
+  HIPCHK(hipMemcpyAsync(sv->tab.p, stage + tab_off, bytes, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_refit_batch(plan, sv->tab.p, c->stream));
+  TravParams p = params(sv);
+  p.n_list = (uint32_t)slots.size();
+  HIPCHK(launch_admit(p, c->stream));
+  sv->n_active += (uint32_t)slots.size();
+  std::lock_guard<std::mutex> g(sv->mu);
+  sv->stats.admitted += slots.size();
+  return GDIST_OK;
+}
+
+// One device step.  Returns a non-OK status only for device failures.
+gdist_status_t step(gdist_server* sv) {
+  gdist_ctx* c = sv->c;
+  // 1. admission
+  std::vector<Pending> reqs;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    const uint64_t room = (uint64_t)sv->seg_f * (sv->nb + 1) / 4;
+    while (!sv->pending.empty() && !sv->free_slots.empty() && sv->n_active + reqs.size() < sv->concurrency &&
+           sv->live_total < room && reqs.size() < sv->free_slots.size()) {
+      reqs.push_back(sv->pending.front());
+      sv->pending.pop_front();
+    }
+  }
+  if (!reqs.empty()) {
+    gdist_status_t s = admit(sv, reqs);
+    if (s != GDIST_OK) return s;
+  }
+  if (sv->n_active == 0) return GDIST_OK;
+  // 2. traversal step
+  TravParams p = params(sv);
+  Ctl hctl;
+  HIPCHK(hipEventRecord(sv->ev[0], c->stream));
+  HIPCHK(launch_traverse(p, c->trav_blocks, c->trav_threads, c->stream));
+  HIPCHK(hipEventRecord(sv->ev[1], c->stream));
+  HIPCHK(hipMemcpyAsync(&hctl, sv->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, sv->ev[0], sv->ev[1]));
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->stats.steps++;
+    sv->stats.rounds += hctl.rounds_done;
+    sv->stats.device_ms += ms;
+  }
+  if (hctl.abort) return fail(GDIST_E_DEVICE, "server step: grid barrier timed out");
+  if (hctl.overflow & 3u) {
+    // the fronts lost entries: every query in flight starts over later
+    std::vector<uint32_t> act;
+    for (uint32_t s = 0; s < sv->S; ++s)
+      if (sv->active[s]) act.push_back(s);
+    bool requeue = act.size() > 1;
+    if (!requeue) {
+      gdist_status_t g = grow_storage(sv);
+      if (g == GDIST_OK) requeue = true;
+      else if (g != GDIST_E_CAPACITY) return g;
+    }
+    if (!requeue) {
+      const Pending& rq = sv->slot_req[act[0]];
+      complete(sv, rq.tag, rq.t_submit, failed_result(GDIST_E_CAPACITY));
+    } else {
+      std::lock_guard<std::mutex> g(sv->mu);
+      for (auto it = act.rbegin(); it != act.rend(); ++it) sv->pending.push_front(sv->slot_req[*it]);
+      sv->stats.requeued += act.size();
+    }
+    for (uint32_t s : act) {
+      sv->active[s] = 0;
+      sv->free_slots.push_back(s);
+    }
+    sv->n_active = 0;
+    sv->live_total = 0;
+    sv->concurrency = sv->concurrency > 1 ? sv->concurrency / 2 : 1;
+    sv->clean_steps = 0;
+    return reset_storage(sv);
+  }
+  sv->round0 += hctl.rounds_done;
+  // 3. live entries per slot
+  p = params(sv);
+  HIPCHK(hipMemsetAsync(sv->live.p, 0, 4ull * sv->S, c->stream));
+  HIPCHK(launch_slot_hist(p, (uint32_t*)sv->live.p, c->stream));
+  std::vector<uint32_t> live(sv->S);
+  std::vector<SlotState> hst(sv->S);
+  HIPCHK(hipMemcpyAsync(live.data(), sv->live.p, 4ull * sv->S, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(hst.data(), sv->st.p, sizeof(SlotState) * sv->S, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  // 4. completions
+  std::vector<uint32_t> fin, bad;
+  uint64_t total = 0;
+  for (uint32_t s = 0; s < sv->S; ++s) {
+    if (!sv->active[s]) continue;
+    total += live[s];
+    if (live[s] != 0) continue;
+    if (hst[s].cand_overflow) bad.push_back(s);
+    else fin.push_back(s);
+  }
+  sv->live_total = total;
+  if (++sv->clean_steps > 16 && sv->concurrency < sv->S) {
+    sv->concurrency++;
+    sv->clean_steps = 0;
+  }
+  for (uint32_t s : bad) {
+    const Pending& rq = sv->slot_req[s];
+    complete(sv, rq.tag, rq.t_submit, failed_result(GDIST_E_CAPACITY));
+  }
+  if (!fin.empty()) {
+    char* stage = (char*)sv->pinned;
+    const size_t list_off = sizeof(SlotDesc) * sv->S;
+    std::memcpy(stage + list_off, fin.data(), 4 * fin.size());
+    HIPCHK(hipMemcpyAsync(sv->list.p, stage + list_off, 4 * fin.size(), hipMemcpyHostToDevice, c->stream));
+    p = params(sv);
+    p.n_list = (uint32_t)fin.size();
+    HIPCHK(launch_reeval(p, c->stream));
+    std::vector<gdist_result_t> out(fin.size());
+    for (size_t i = 0; i < fin.size(); ++i)
+      HIPCHK(hipMemcpyAsync(&out[i], (gdist_result_t*)sv->res.p + fin[i], sizeof(gdist_result_t),
+                            hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < fin.size(); ++i) {
+      const Pending& rq = sv->slot_req[fin[i]];
+      complete(sv, rq.tag, rq.t_submit, out[i]);
+    }
+  }
+  for (uint32_t s : bad) fin.push_back(s);
+  for (uint32_t s : fin) {
+    sv->active[s] = 0;
+    sv->free_slots.push_back(s);
+    sv->n_active--;
+  }
+  return GDIST_OK;
+}
+
+void worker_main(gdist_server* sv) {
+  (void)hipSetDevice(sv->c->device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      if (sv->stopping.load()) break;
+      if (sv->pending.empty() && sv->n_active == 0) {
+        sv->cv.wait_for(lk, std::chrono::milliseconds(2));
+        continue;
+      }
+    }
+    gdist_status_t s = step(sv);
+    if (s != GDIST_OK) {
+      // device failure: fail everything in flight and queued, then stop
+      for (uint32_t i = 0; i < sv->S; ++i)
+        if (sv->active[i]) complete(sv, sv->slot_req[i].tag, sv->slot_req[i].t_submit, failed_result(s));
+      std::deque<Pending> q;
+      {
+        std::lock_guard<std::mutex> g(sv->mu);
+        q.swap(sv->pending);
+      }
+      for (const Pending& rq : q) complete(sv, rq.tag, rq.t_submit, failed_result(s));
+      sv->n_active = 0;
+      break;
+    }
+  }
+}
+
+void free_server(gdist_server* sv) {
+  gdist_ctx* c = sv->c;
+  DevBuf* bufs[] = {&sv->desc, &sv->st,  &sv->res,    &sv->boxes, &sv->front[0], &sv->front[1], &sv->leaf[0],
+                    &sv->leaf[1], &sv->counts, &sv->cand, &sv->cand64, &sv->ctl,   &sv->live,     &sv->list, &sv->tab};
+  for (DevBuf* b : bufs) release_buf(c, *b);
+  if (sv->pinned) (void)hipHostFree(sv->pinned);
+  for (int i = 0; i < 2; ++i)
+    if (sv->ev[i]) (void)hipEventDestroy(sv->ev[i]);
+}
+
+}  // namespace
+
+extern "C" {
+
+gdist_status_t gdist_server_start(gdist_ctx_t c, const gdist_server_config_t* config, gdist_server_t* out) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (!out) return fail(GDIST_E_INVALID, "NULL output pointer");
+  *out = nullptr;
+  if (c->busy) return fail(GDIST_E_BUSY, "the context already runs a server");
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  gdist_server* sv = new gdist_server();
+  sv->c = c;
+  if (config) sv->cfg = *config;
+  gdist_server_config_t& cf = sv->cfg;
+  if (cf.max_slots == 0) cf.max_slots = 64;
+  if (cf.rounds_per_step == 0) cf.rounds_per_step = 4;
+  if (cf.front_capacity == 0) cf.front_capacity = 1ull << 25;
+  if (cf.cand_per_slot == 0) cf.cand_per_slot = 1u << 17;
+  if (cf.max_tris == 0)
+    for (auto& kv : c->meshes) cf.max_tris = std::max(cf.max_tris, kv.second->n_tris);
+  if (cf.max_slots > 512 || cf.max_tris == 0 || cf.front_capacity > kServerCapLimit ||
+      cf.cand_per_slot > (1u << 26)) {
+    delete sv;
+    return fail(GDIST_E_INVALID, "server config out of range (max_slots <= 512, a mesh or max_tris > 0, "
+                                 "front_capacity <= 2^28, cand_per_slot <= 2^26)");
+  }
+  sv->S = cf.max_slots;
+  sv->nb = c->trav_blocks;
+  sv->max_leaves = 1u << (31 - __builtin_clz(cf.max_tris));
+  sv->box_stride = (12ull * sv->max_leaves + 63) & ~(size_t)63;
+  sv->seg_f = (uint32_t)std::max<uint64_t>(cf.front_capacity / (sv->nb + 1), sv->S);
+  sv->seg_l = sv->seg_f;
+  sv->cps = cf.cand_per_slot;
+  sv->concurrency = sv->S;
+  const uint64_t fcap = (uint64_t)sv->seg_f * (sv->nb + 1);
+  gdist_status_t s = GDIST_OK;
+  auto A = [&](DevBuf& b, size_t bytes) {
+    if (s == GDIST_OK) s = ensure(c, b, bytes);
+  };
+  A(sv->desc, sizeof(SlotDesc) * sv->S);
+  A(sv->st, sizeof(SlotState) * sv->S);
+  A(sv->res, sizeof(gdist_result_t) * sv->S);
+  A(sv->boxes, sizeof(float) * sv->box_stride * sv->S);
+  for (int b = 0; b < 2; ++b) {
+    A(sv->front[b], 16ull * fcap);
+    A(sv->leaf[b], 16ull * fcap);
+  }
+  A(sv->counts, 16ull * (sv->nb + 1));
+  A(sv->cand, sizeof(Cand) * (size_t)sv->cps * sv->S);
+  A(sv->cand64, sizeof(double) * (size_t)sv->cps * sv->S);
+  A(sv->ctl, sizeof(Ctl));
+  A(sv->live, 4ull * sv->S);
+  A(sv->list, 4ull * sv->S);
+  A(sv->tab, sizeof(RefitJob) * sv->S + sizeof(ReduceJob) * sv->S * kMaxRefitPasses + 256);
+  if (s == GDIST_OK) {
+    sv->pinned_bytes = tab_offset(sv) + sv->tab.bytes;
+    if (hipHostMalloc(&sv->pinned, sv->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      sv->pinned = nullptr;
+      s = fail(GDIST_E_OOM, "hipHostMalloc for the server failed");
+    }
+  }
+  if (s == GDIST_OK && (hipEventCreate(&sv->ev[0]) != hipSuccess || hipEventCreate(&sv->ev[1]) != hipSuccess))
+    s = fail(GDIST_E_DEVICE, "hipEventCreate failed");
+  if (s == GDIST_OK) s = reset_storage(sv);
+  if (s == GDIST_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = fail(GDIST_E_DEVICE, "server reset failed");
+  if (s != GDIST_OK) {
+    std::string msg = gdist_last_error();
+    free_server(sv);
+    delete sv;
+    fail(s, "%s", msg.c_str());
+    return s;
+  }
+  sv->active.assign(sv->S, 0);
+  sv->slot_req.resize(sv->S);
+  for (uint32_t i = 0; i < sv->S; ++i) sv->free_slots.push_back(sv->S - 1 - i);
+  c->busy = true;
+  sv->worker = std::thread(worker_main, sv);
+  *out = sv;
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_server_submit(gdist_server_t sv, const gdist_query_desc_t* q, uint64_t tag) {
+  if (!sv) return fail(GDIST_E_HANDLE, "NULL server");
+  if (!q) return fail(GDIST_E_INVALID, "NULL query");
+  SlotDesc d;
+  Mesh* B = nullptr;
+  gdist_status_t s = make_slot(sv->c, *q, 0, &d, &B);
+  if (s != GDIST_OK) return s;
+  if (B->L > sv->max_leaves)
+    return fail(GDIST_E_CAPACITY, "mesh of %u triangles exceeds the server's max_tris", B->n_tris);
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->pending.push_back(Pending{*q, tag, now_ns()});
+    sv->stats.submitted++;
+  }
+  sv->cv.notify_one();
+  return GDIST_OK;
+}
+
+uint32_t gdist_server_poll(gdist_server_t sv, gdist_completion_t* out, uint32_t max) {
+  if (!sv || !out || max == 0) return 0;
+  std::lock_guard<std::mutex> g(sv->mu);
+  uint32_t n = (uint32_t)std::min<size_t>(max, sv->done.size());
+  for (uint32_t i = 0; i < n; ++i) out[i] = sv->done[i];
+  sv->done.erase(sv->done.begin(), sv->done.begin() + n);
+  return n;
+}
+
+gdist_status_t gdist_server_stats(gdist_server_t sv, gdist_server_stats_t* out) {
+  if (!sv) return fail(GDIST_E_HANDLE, "NULL server");
+  if (!out) return fail(GDIST_E_INVALID, "NULL output");
+  std::lock_guard<std::mutex> g(sv->mu);
+  *out = sv->stats;
+  out->active = sv->n_active;
+  out->pending = (uint32_t)sv->pending.size();
+  out->concurrency = sv->concurrency;
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_server_stop(gdist_server_t sv) {
+  if (!sv) return GDIST_OK;
+  sv->stopping.store(true);
+  sv->cv.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  (void)hipSetDevice(sv->c->device);
+  (void)hipStreamSynchronize(sv->c->stream);
+  free_server(sv);
+  sv->c->busy = false;
+  delete sv;
+  return GDIST_OK;
+}
+
+}  // extern "C"

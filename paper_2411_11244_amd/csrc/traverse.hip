@@ -206,21 +206,24 @@ __device__ __forceinline__ float sep_lower(const V3<float>* P, const V3<float>* 
   return lb;
 }
 
-// Zero the control block and the round-0 segment counts.
+// Zero the control block and the segment counts of the first round's buffers.
 __global__ void k_reset(TravParams p) {
   uint32_t* w = reinterpret_cast<uint32_t*>(p.ctl);
   for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) w[i] = 0u;
-  for (uint32_t i = threadIdx.x; i < p.nblocks; i += blockDim.x) {
-    p.fcount[0][i] = 0u;
-    p.lcount[0][i] = 0u;
+  const uint32_t cur = p.round0 & 1u;
+  for (uint32_t i = threadIdx.x; i <= p.nblocks; i += blockDim.x) {
+    p.fcount[cur][i] = 0u;
+    p.lcount[cur][i] = 0u;
   }
 }
 
-// One wave per query: error window, root bounds, greedy dive, root entry.
-__global__ __launch_bounds__(kTravThreads) void k_init(TravParams p) {
+// One wave per admitted query: error window, root bounds, greedy dive, and
+// its root pair appended to the admission segment of the next round's input.
+__global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
   const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t s = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (s >= p.n_slots) return;
+  const uint32_t li = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (li >= p.n_list) return;
+  const uint32_t s = p.slot_list ? p.slot_list[li] : li;
   const SlotDesc& d = p.desc[s];
   const uint32_t mode = d.mode;
   const bool enh = d.enhanced != 0;
@@ -303,6 +306,8 @@ __global__ __launch_bounds__(kTravThreads) void k_init(TravParams p) {
     st.delta = delta;
     st.n_ties = 0;
     st.n_admitted = 0;
+    st.n_cand = 0;
+    st.cand_overflow = 0;
     st.key_pair = ~0ull;
     st.best = fbits(best);
     st.best32 = mode == 0 ? fbits(__builtin_huge_valf()) : 0u;
@@ -310,14 +315,17 @@ __global__ __launch_bounds__(kTravThreads) void k_init(TravParams p) {
     gdist_result_t& r = p.res[s];
     r.status = GDIST_E_DEVICE;
     r.flags = 0;
-    // root pairs enter round 0 through the segment of workgroup 0
+    // root pairs enter the next round through the admission segment
+    const uint32_t cur = p.round0 & 1u, nb = p.nblocks;
     uint4 e = make_uint4(1u, 1u, fbits(key), s);
     if (d.LA == 1 && d.LB == 1) {
-      uint32_t i = atomicAdd(&p.lcount[0][0], 1u);
-      p.leaf[0][i] = e;
+      uint32_t i = atomicAdd(&p.lcount[cur][nb], 1u);
+      if (i < p.seg_leaf) p.leaf[cur][(uint64_t)nb * p.seg_leaf + i] = e;
+      else atomicOr(&p.ctl->overflow, 2u);
     } else {
-      uint32_t i = atomicAdd(&p.fcount[0][0], 1u);
-      p.front[0][i] = e;
+      uint32_t i = atomicAdd(&p.fcount[cur][nb], 1u);
+      if (i < p.seg_front) p.front[cur][(uint64_t)nb * p.seg_front + i] = e;
+      else atomicOr(&p.ctl->overflow, 1u);
     }
   }
 }
@@ -331,8 +339,8 @@ constexpr uint32_t kMaxBlocks = 1024;
 constexpr uint32_t kLdsSlots = 512;
 
 struct BlockState {
-  uint32_t fpre[kMaxBlocks + 1];   // prefix of the current front's segment counts
-  uint32_t lpre[kMaxBlocks + 1];   // same for the leaf-pair buffer
+  uint32_t fpre[kMaxBlocks + 2];   // prefix of the current front's segment counts
+  uint32_t lpre[kMaxBlocks + 2];   // (workgroup segments + admission segment)
   uint32_t scan[kTravBlock];
   uint32_t fo, lo;                 // this workgroup's appends in the current round
   uint32_t best[kLdsSlots];        // per-slot running bound (float bits), refreshed each round
@@ -600,12 +608,21 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
     }
   }
   add_stat(ws, ST_FULL, act);
-  Cand ce;
-  ce.d32 = dd;
-  ce.slot = slot;
-  ce.ia = pa;
-  ce.ib = pb;
-  append(act && cand, ce, p.cand, &c->cand_len, p.cand_cap, &c->overflow, 4u, lane, lt);
+  if (act && cand) {
+    // candidates are rare: one atomic per candidate on its slot's counter
+    uint32_t idx = atomicAdd(&p.st[slot].n_cand, 1u);
+    if (idx < p.cand_per_slot) {
+      Cand ce;
+      ce.d32 = dd;
+      ce.slot = slot;
+      ce.ia = pa;
+      ce.ib = pb;
+      p.cand[(uint64_t)slot * p.cand_per_slot + idx] = ce;
+    } else {
+      atomicOr(&p.st[slot].cand_overflow, 1u);
+      if (p.cand_stop) atomicOr(&c->overflow, 4u);
+    }
+  }
   add_stat(ws, ST_CAND, act && cand);
   improve_best(p, bs, lds, act, slot, mode, improve, lane);
   improve_bound(&p.st[0].best32, sizeof(SlotState) / 4, act, slot, mode, dd, lane);
@@ -648,10 +665,11 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   if (lds_slots)
     for (uint32_t s = tid; s < p.n_slots; s += kTravBlock) bs->delta[s] = p.st[s].delta;
 
-  for (uint32_t round = 0;; ++round) {
+  for (uint32_t r = 0; r < p.max_rounds; ++r) {
     if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) break;
+    const uint32_t round = p.round0 + r;   // global round: selects the buffer parity
     Round rd;
-    rd.nb = gridDim.x;
+    rd.nb = gridDim.x + 1u;                // workgroup segments + the admission segment
     rd.seg_f = p.seg_front;
     rd.seg_l = p.seg_leaf;
     rd.lds_slots = lds_slots;
@@ -669,10 +687,10 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     if (blockIdx.x == 0 && tid == 0) {
       bs->stats[ST_ROUNDS] += 1ull;
       if (n > bs->stats[ST_PEAK]) bs->stats[ST_PEAK] = n;
-      if (round < kTraceRounds) {
-        c->trace_t[round] = (unsigned long long)wall_clock64();
-        c->trace_n[round] = n;
-        c->trace_nl[round] = nl;
+      if (r < kTraceRounds) {
+        c->trace_t[r] = (unsigned long long)wall_clock64();
+        c->trace_n[r] = n;
+        c->trace_nl[r] = nl;
       }
     }
     uint32_t k = p.k_cap;
@@ -705,12 +723,19 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     if (tid == 0) {
       p.fcount[(round + 1u) & 1u][blockIdx.x] = bs->fo < rd.seg_f ? bs->fo : rd.seg_f;
       p.lcount[(round + 1u) & 1u][blockIdx.x] = bs->lo < rd.seg_l ? bs->lo : rd.seg_l;
+      if (blockIdx.x == 0) {
+        p.fcount[(round + 1u) & 1u][gridDim.x] = 0u;   // admission segment consumed
+        p.lcount[(round + 1u) & 1u][gridDim.x] = 0u;
+      }
       bs->fo = 0u;
       bs->lo = 0u;
     }
     grid_sync(c, p.spin_limit);
   }
-  if (blockIdx.x == 0 && tid == 0) c->trace_end = (unsigned long long)wall_clock64();
+  if (blockIdx.x == 0 && tid == 0) {
+    c->trace_end = (unsigned long long)wall_clock64();
+    c->rounds_done = (uint32_t)bs->stats[ST_ROUNDS];
+  }
   if (lane == 0)
     for (int i = 0; i < ST_N; ++i)
       if (i != ST_ROUNDS && i != ST_PEAK && ws.v[i]) atomicAdd(&bs->stats[i], (unsigned long long)ws.v[i]);
@@ -723,24 +748,39 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   }
 }
 
-// FP64 re-evaluation, in three grid-wide steps (separate launches).
+// FP64 re-evaluation, in three grid-wide steps (separate launches), over the
+// listed slots.  Workgroups [i * G, (i+1) * G) serve the i-th listed slot and
+// walk its candidate region.
 // A: admit the candidates inside the final window and evaluate them in FP64
 //    in the world frame from the caller's FP32 vertices and FP64 poses.
-__global__ __launch_bounds__(kTravThreads) void k_reeval_values(TravParams p) {
+struct ReevalRange {
+  uint32_t slot, begin, stride, end;
+};
+__device__ __forceinline__ ReevalRange reeval_range(const TravParams& p, uint32_t G) {
+  ReevalRange r;
+  const uint32_t i = blockIdx.x / G, part = blockIdx.x % G;
+  r.slot = p.slot_list ? p.slot_list[i] : i;
+  uint32_t n = p.st[r.slot].n_cand;
+  r.end = n < p.cand_per_slot ? n : p.cand_per_slot;
+  r.begin = part * kTravThreads + threadIdx.x;
+  r.stride = G * kTravThreads;
+  return r;
+}
+
+__global__ __launch_bounds__(kTravThreads) void k_reeval_values(TravParams p, uint32_t G) {
   Ctl* c = p.ctl;
   if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) return;
-  const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t nt = (uint64_t)gridDim.x * blockDim.x;
-  uint32_t ncand = ld_rlx(&c->cand_len);
-  if (ncand > p.cand_cap) ncand = p.cand_cap;
-  for (uint64_t i = gt; i < ncand; i += nt) {
-    Cand cd = p.cand[i];
-    const SlotDesc& d = p.desc[cd.slot];
-    SlotState& st = p.st[cd.slot];
-    const float best = bitsf(ld_rlx(&st.best));
+  const ReevalRange rr = reeval_range(p, G);
+  const SlotDesc& d = p.desc[rr.slot];
+  SlotState& st = p.st[rr.slot];
+  const Cand* cands = p.cand + (uint64_t)rr.slot * p.cand_per_slot;
+  double* d64 = p.cand_d64 + (uint64_t)rr.slot * p.cand_per_slot;
+  const float best = bitsf(ld_rlx(&st.best));
+  for (uint32_t i = rr.begin; i < rr.end; i += rr.stride) {
+    Cand cd = cands[i];
     const bool adm = d.mode == 0 ? (cd.d32 - st.delta <= best) : (cd.d32 + st.delta >= best);
     if (!adm) {
-      p.cand_d64[i] = -1.0;
+      d64[i] = -1.0;
       continue;
     }
     V3<double> P[3], Q[3];
@@ -749,7 +789,7 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_values(TravParams p) {
     double d2 = d.mode == 0 ? tri_tri_min_d2<double, false>(P, Q, nullptr, nullptr)
                             : tri_tri_max_d2<double, false>(P, Q, nullptr, nullptr);
     double dd = sqrt(d2);
-    p.cand_d64[i] = dd;
+    d64[i] = dd;
     unsigned long long b = (unsigned long long)__double_as_longlong(dd);
     if (d.mode == 0) atomicMin(&st.key_d, b);
     else atomicMax(&st.key_d, b);
@@ -763,41 +803,38 @@ __device__ __forceinline__ unsigned long long caller_pair(const SlotDesc& d, con
 }
 
 // B: the tie set and its lexicographically smallest caller pair.
-__global__ __launch_bounds__(kTravThreads) void k_reeval_ties(TravParams p) {
+__global__ __launch_bounds__(kTravThreads) void k_reeval_ties(TravParams p, uint32_t G) {
   Ctl* c = p.ctl;
   if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) return;
-  const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t nt = (uint64_t)gridDim.x * blockDim.x;
-  uint32_t ncand = ld_rlx(&c->cand_len);
-  if (ncand > p.cand_cap) ncand = p.cand_cap;
-  for (uint64_t i = gt; i < ncand; i += nt) {
-    double dd = p.cand_d64[i];
+  const ReevalRange rr = reeval_range(p, G);
+  const SlotDesc& d = p.desc[rr.slot];
+  SlotState& st = p.st[rr.slot];
+  const Cand* cands = p.cand + (uint64_t)rr.slot * p.cand_per_slot;
+  const double* d64 = p.cand_d64 + (uint64_t)rr.slot * p.cand_per_slot;
+  const double D = __longlong_as_double((long long)st.key_d);
+  for (uint32_t i = rr.begin; i < rr.end; i += rr.stride) {
+    double dd = d64[i];
     if (dd < 0.0) continue;
-    Cand cd = p.cand[i];
-    const SlotDesc& d = p.desc[cd.slot];
-    SlotState& st = p.st[cd.slot];
-    double D = __longlong_as_double((long long)st.key_d);
     if (fabs(dd - D) <= d.tau) {
-      atomicMin(&st.key_pair, caller_pair(d, cd));
+      atomicMin(&st.key_pair, caller_pair(d, cands[i]));
       atomicAdd(&st.n_ties, 1u);
     }
   }
 }
 
 // C: closest (farthest) points of the reported pair, and the per-query summary.
-__global__ __launch_bounds__(kTravThreads) void k_reeval_report(TravParams p) {
+__global__ __launch_bounds__(kTravThreads) void k_reeval_report(TravParams p, uint32_t G) {
   Ctl* c = p.ctl;
   if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) return;
-  const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t nt = (uint64_t)gridDim.x * blockDim.x;
-  uint32_t ncand = ld_rlx(&c->cand_len);
-  if (ncand > p.cand_cap) ncand = p.cand_cap;
-  for (uint64_t i = gt; i < ncand; i += nt) {
-    double dd = p.cand_d64[i];
-    if (dd < 0.0) continue;
-    Cand cd = p.cand[i];
-    const SlotDesc& d = p.desc[cd.slot];
-    const SlotState& st = p.st[cd.slot];
+  const ReevalRange rr = reeval_range(p, G);
+  const SlotDesc& d = p.desc[rr.slot];
+  const SlotState& st = p.st[rr.slot];
+  const Cand* cands = p.cand + (uint64_t)rr.slot * p.cand_per_slot;
+  const double* d64 = p.cand_d64 + (uint64_t)rr.slot * p.cand_per_slot;
+  gdist_result_t& res = p.res[rr.slot];
+  for (uint32_t i = rr.begin; i < rr.end; i += rr.stride) {
+    if (d64[i] < 0.0) continue;
+    const Cand cd = cands[i];
     unsigned long long key = caller_pair(d, cd);
     if (key != st.key_pair) continue;
     V3<double> P[3], Q[3], x, y;
@@ -805,36 +842,67 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_report(TravParams p) {
     world_tri(d.trisB, cd.ib, d.RB, d.tB, Q);
     if (d.mode == 0) tri_tri_min_d2<double, true>(P, Q, &x, &y);
     else tri_tri_max_d2<double, true>(P, Q, &x, &y);
-    gdist_result_t& r = p.res[cd.slot];
     V3<double> qa = d.swapped ? y : x, qb = d.swapped ? x : y;
-    r.point_a[0] = qa.x; r.point_a[1] = qa.y; r.point_a[2] = qa.z;
-    r.point_b[0] = qb.x; r.point_b[1] = qb.y; r.point_b[2] = qb.z;
-    r.tri_a = (uint32_t)(key >> 32);
-    r.tri_b = (uint32_t)(key & 0xffffffffull);
+    res.point_a[0] = qa.x; res.point_a[1] = qa.y; res.point_a[2] = qa.z;
+    res.point_b[0] = qb.x; res.point_b[1] = qb.y; res.point_b[2] = qb.z;
+    res.tri_a = (uint32_t)(key >> 32);
+    res.tri_b = (uint32_t)(key & 0xffffffffull);
   }
-  for (uint64_t s = gt; s < p.n_slots; s += nt) {
-    const SlotDesc& d = p.desc[s];
-    const SlotState& st = p.st[s];
-    gdist_result_t& r = p.res[s];
-    r.n_candidates = st.n_admitted;
-    r.n_ties = st.n_ties;
-    r.distance_fp32 = (double)bitsf(st.best32);
-    r.err_bound = d.err_bound;
+  if (blockIdx.x % G == 0 && threadIdx.x == 0) {
+    res.n_candidates = st.n_admitted;
+    res.n_ties = st.n_ties;
+    res.distance_fp32 = (double)bitsf(st.best32);
+    res.err_bound = d.err_bound;
+    res.flags = 0;
     if (st.n_admitted == 0u) {
-      r.status = GDIST_E_DEVICE;
-      r.distance = __longlong_as_double(0x7ff8000000000000ll);
-      continue;
+      res.status = GDIST_E_DEVICE;
+      res.distance = __longlong_as_double(0x7ff8000000000000ll);
+    } else {
+      double D = __longlong_as_double((long long)st.key_d);
+      res.distance = D;
+      res.status = GDIST_OK;
+      res.flags = (st.n_ties > 1u ? GDIST_F_TIED : 0u) | ((d.mode == 0 && D == 0.0) ? GDIST_F_ZERO : 0u);
     }
-    double D = __longlong_as_double((long long)st.key_d);
-    r.distance = D;
-    r.status = GDIST_OK;
-    r.flags = (st.n_ties > 1u ? GDIST_F_TIED : 0u) | ((d.mode == 0 && D == 0.0) ? GDIST_F_ZERO : 0u);
   }
 }
 
-hipError_t launch_init(const TravParams& p, hipStream_t s) {
+// Live entries per slot in the current front and leaf buffers (after a step):
+// workgroup b counts segment b of each (the last workgroup the admission
+// segment) in LDS and adds its non-zero counts to live[].
+__global__ __launch_bounds__(kTravThreads) void k_slot_hist(TravParams p, uint32_t* __restrict__ live) {
+  __shared__ uint32_t h[kLdsSlots];
+  for (uint32_t i = threadIdx.x; i < p.n_slots; i += kTravThreads) h[i] = 0u;
+  __syncthreads();
+  const uint32_t cur = p.round0 & 1u, b = blockIdx.x;
+  const uint32_t nf = p.fcount[cur][b], nl = p.lcount[cur][b];
+  const uint4* fs = p.front[cur] + (uint64_t)b * p.seg_front;
+  const uint4* ls = p.leaf[cur] + (uint64_t)b * p.seg_leaf;
+  for (uint32_t i = threadIdx.x; i < nf; i += kTravThreads) atomicAdd(&h[fs[i].w], 1u);
+  for (uint32_t i = threadIdx.x; i < nl; i += kTravThreads) atomicAdd(&h[ls[i].w], 1u);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < p.n_slots; i += kTravThreads)
+    if (h[i]) atomicAdd(&live[i], h[i]);
+}
+
+uint32_t reeval_groups(uint32_t n_list) {
+  uint32_t g = 1024u / (n_list ? n_list : 1u);
+  return g < 1u ? 1u : (g > 64u ? 64u : g);
+}
+
+hipError_t launch_reset(const TravParams& p, hipStream_t s) {
   k_reset<<<1, 256, 0, s>>>(p);
-  k_init<<<(p.n_slots + kWavesPerBlock - 1) / kWavesPerBlock, kTravThreads, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t launch_admit(const TravParams& p, hipStream_t s) {
+  if (p.n_list == 0) return hipSuccess;
+  k_admit<<<(p.n_list + kWavesPerBlock - 1) / kWavesPerBlock, kTravThreads, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_hist(const TravParams& p, uint32_t* live, hipStream_t s) {
+  if (p.n_slots > kLdsSlots) return hipErrorInvalidValue;
+  k_slot_hist<<<p.nblocks + 1, kTravThreads, 0, s>>>(p, live);
   return hipGetLastError();
 }
 
@@ -861,10 +929,12 @@ hipError_t launch_traverse(const TravParams& p, uint32_t blocks, uint32_t thread
   return hipLaunchCooperativeKernel((const void*)k_traverse, dim3(blocks), dim3(threads), args, 0, s);
 }
 
-hipError_t launch_reeval(const TravParams& p, uint32_t blocks, hipStream_t s) {
-  k_reeval_values<<<blocks, kTravThreads, 0, s>>>(p);
-  k_reeval_ties<<<blocks, kTravThreads, 0, s>>>(p);
-  k_reeval_report<<<blocks, kTravThreads, 0, s>>>(p);
+hipError_t launch_reeval(const TravParams& p, hipStream_t s) {
+  if (p.n_list == 0) return hipSuccess;
+  const uint32_t G = reeval_groups(p.n_list);
+  k_reeval_values<<<p.n_list * G, kTravThreads, 0, s>>>(p, G);
+  k_reeval_ties<<<p.n_list * G, kTravThreads, 0, s>>>(p, G);
+  k_reeval_report<<<p.n_list * G, kTravThreads, 0, s>>>(p, G);
   return hipGetLastError();
 }
 

@@ -70,6 +70,26 @@ class gdist_stats_t(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class gdist_server_config_t(C.Structure):
+    _fields_ = [("max_slots", C.c_uint32), ("rounds_per_step", C.c_uint32), ("front_capacity", C.c_uint64),
+                ("cand_per_slot", C.c_uint32), ("max_tris", C.c_uint32)]
+
+
+class gdist_completion_t(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("t_submit_ns", C.c_uint64), ("t_done_ns", C.c_uint64),
+                ("result", gdist_result_t)]
+
+
+class gdist_server_stats_t(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "admitted", "completed", "failed", "requeued",
+                                          "steps", "rounds")] + \
+               [(n, C.c_uint32) for n in ("active", "pending", "concurrency", "reserved")] + \
+               [("device_ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 _lib = None
 
 
@@ -97,11 +117,17 @@ def lib():
         "gdist_last_stats": [vp, C.POINTER(gdist_stats_t)],
         "gdist_eval_box_bounds": [vp, u32, fp, fp, fp],
         "gdist_eval_tri_tri": [vp, u32, fp, fp, u32, fp, dp],
+        "gdist_server_start": [vp, C.POINTER(gdist_server_config_t), C.POINTER(vp)],
+        "gdist_server_submit": [vp, C.POINTER(gdist_query_desc_t), u64],
+        "gdist_server_stats": [vp, C.POINTER(gdist_server_stats_t)],
+        "gdist_server_stop": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = st
+    L.gdist_server_poll.argtypes = [vp, C.POINTER(gdist_completion_t), u32]
+    L.gdist_server_poll.restype = u32
     L.gdist_last_error.argtypes = []
     L.gdist_last_error.restype = C.c_char_p
     _lib = L
@@ -111,7 +137,9 @@ def lib():
 def exported_symbols() -> List[str]:
     return ["gdist_create", "gdist_destroy", "gdist_set_option", "gdist_build", "gdist_release",
             "gdist_mesh_info", "gdist_mesh_export", "gdist_query", "gdist_query_batch",
-            "gdist_last_stats", "gdist_last_error", "gdist_eval_box_bounds", "gdist_eval_tri_tri"]
+            "gdist_last_stats", "gdist_last_error", "gdist_eval_box_bounds", "gdist_eval_tri_tri",
+            "gdist_server_start", "gdist_server_submit", "gdist_server_poll", "gdist_server_stats",
+            "gdist_server_stop"]
 
 
 def gdist_last_error() -> str:
@@ -254,6 +282,41 @@ def gdist_eval_tri_tri(ctx: int, p, q, mode: int = 0):
     _check(lib().gdist_eval_tri_tri(ctx, p.shape[0], p.ctypes.data, q.ctypes.data, int(mode),
                                     o32.ctypes.data, o64.ctypes.data))
     return o32, o64
+
+
+# ------------------------------------------------------------------ serving
+def gdist_server_start(ctx: int, max_slots: int = 0, rounds_per_step: int = 0, front_capacity: int = 0,
+                       cand_per_slot: int = 0, max_tris: int = 0) -> int:
+    cfg = gdist_server_config_t(max_slots, rounds_per_step, front_capacity, cand_per_slot, max_tris)
+    h = C.c_void_p()
+    _check(lib().gdist_server_start(ctx, C.byref(cfg), C.byref(h)))
+    return h.value
+
+
+def gdist_server_submit(srv: int, desc: gdist_query_desc_t, tag: int) -> None:
+    _check(lib().gdist_server_submit(srv, C.byref(desc), int(tag)))
+
+
+def gdist_server_poll(srv: int, max_n: int = 256) -> List[dict]:
+    """Finished queries: dicts with tag, t_submit_ns, t_done_ns and the result fields."""
+    buf = (gdist_completion_t * max_n)()
+    n = lib().gdist_server_poll(srv, buf, max_n)
+    out = []
+    for i in range(n):
+        d = buf[i].result.as_dict()
+        d.update(tag=int(buf[i].tag), t_submit_ns=int(buf[i].t_submit_ns), t_done_ns=int(buf[i].t_done_ns))
+        out.append(d)
+    return out
+
+
+def gdist_server_stats(srv: int) -> dict:
+    s = gdist_server_stats_t()
+    _check(lib().gdist_server_stats(srv, C.byref(s)))
+    return s.as_dict()
+
+
+def gdist_server_stop(srv: int) -> None:
+    _check(lib().gdist_server_stop(srv))
 
 
 class Context:
