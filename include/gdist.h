@@ -137,10 +137,16 @@ gdist_status_t gdist_create(int device, gdist_ctx_t* out);
 gdist_status_t gdist_destroy(gdist_ctx_t ctx);
 
 /* Set a tunable.  Keys (value ranges are checked, E_INVALID otherwise):
- *   "front_capacity"  entries per front buffer (16 B each), initial value
+ *   "front_capacity"  entries per front buffer (16 B each); a round expands at
+ *                     most about a quarter of it, the surplus waits on the
+ *                     spill stack
  *   "leaf_capacity"   leaf pairs per narrow-phase buffer (16 B each)
+ *   "stack_capacity"  spill-stack entries (16 B each), initial value; doubles on
+ *                     overflow up to 2^31
  *   "cand_capacity"   FP64 candidates (24 B each)
  *   "max_retries"     capacity doublings before GDIST_E_CAPACITY
+ *   "group_size"      queries of a batch traversed together per launch (0 = all);
+ *                     smaller groups keep their trees' boxes in the caches
  *   "expand_budget"   C of the adaptive depth rule (largest k with 4^k n < C)
  *   "k_cap"           largest expansion depth per side and round (1..8)
  *   "kappa"           FP32 inflation: delta = kappa * 2^-24 * M
@@ -209,12 +215,16 @@ typedef struct {
   uint32_t max_slots;       /* queries in flight, 1..512 (0 = 64)                        */
   uint32_t rounds_per_step; /* traversal rounds per device step (0 = 4)                  */
   uint64_t front_capacity;  /* entries per front and per leaf-pair buffer (0 = 2^25, at
-                               most 2^28); doubles when one query overflows it alone     */
+                               most 2^28); a step's rounds expand at most about a
+                               quarter of it, the surplus waits on the spill stack       */
   uint32_t cand_per_slot;   /* FP64 candidates per query (0 = 2^17, at most 2^26); a
                                query that needs more fails with GDIST_E_CAPACITY        */
   uint32_t max_tris;        /* largest mesh a query refits, i.e. the smaller mesh of
                                its pair (0 = largest mesh built on the context when the
                                server starts); sizes the per-slot box storage            */
+  uint32_t reserved;
+  uint64_t stack_capacity;  /* spill-stack entries (0 = 2^26, at most 2^31); doubles when
+                               one query overflows it alone                              */
 } gdist_server_config_t;
 
 typedef struct {
@@ -234,8 +244,8 @@ typedef struct {
 } gdist_server_stats_t;
 
 /* Start a server on ctx (config may be NULL for defaults).  Allocates all of
- * its device storage up front (the front buffers grow only as front_capacity
- * says).  E_BUSY if ctx already has a server. */
+ * its device storage up front (only the spill stack grows later, as
+ * stack_capacity says).  E_BUSY if ctx already has a server. */
 gdist_status_t gdist_server_start(gdist_ctx_t ctx, const gdist_server_config_t* config, gdist_server_t* out);
 
 /* Queue one query.  Handles, poses and mode are validated here (E_HANDLE /

@@ -154,6 +154,10 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
     return v < 1u ? 1u : v;
   };
   uint32_t sf = seg_of(c->front_cap), sl = seg_of(c->leaf_cap);
+  const uint32_t smin = min_segment(c->expand_budget, nb);
+  if (sf < smin) sf = smin;
+  if (sl < smin) sl = smin;
+  uint64_t scap = c->stack_cap;
   uint32_t cps = c->cand_cap / gn;
   if (cps < 1024u) cps = 1024u;
   Ctl hctl;
@@ -165,6 +169,7 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
       if ((s = ensure(c, c->front[b], 16ull * fcap)) != GDIST_OK) return s;
       if ((s = ensure(c, c->leaf[b], 16ull * lcap)) != GDIST_OK) return s;
     }
+    if ((s = ensure(c, c->stack, 16ull * scap)) != GDIST_OK) return s;
     if ((s = ensure(c, c->cand, sizeof(Cand) * (size_t)ccap)) != GDIST_OK) return s;
     if ((s = ensure(c, c->cand64, sizeof(double) * (size_t)ccap)) != GDIST_OK) return s;
     TravParams p;
@@ -197,6 +202,9 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
     p.k_cap = c->k_cap;
     p.spin_limit = 1u << 26;
     p.cand_stop = 1u;
+    p.stack = (uint4*)c->stack.p;
+    p.stack_cap = (uint32_t)scap;
+    p.round_cap = round_cap_for(sf < sl ? sf : sl, nb);
     HIPCHK(launch_reset(p, c->stream));
     HIPCHK(launch_admit(p, c->stream));
     if (*first_launch) HIPCHK(hipEventRecord(c->ev[2], c->stream));
@@ -218,21 +226,26 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
       // keep grown capacities for the next queries on this context
       if (fcap > c->front_cap) c->front_cap = (uint32_t)fcap;
       if (lcap > c->leaf_cap) c->leaf_cap = (uint32_t)lcap;
+      if (scap > c->stack_cap) c->stack_cap = scap;
       if (ccap > c->cand_cap) c->cand_cap = (uint32_t)(ccap < kCandLimit ? ccap : kCandLimit);
       break;
     }
     const bool can_grow = ((hctl.overflow & 1u) == 0 || 2ull * fcap <= kCapLimit) &&
                           ((hctl.overflow & 2u) == 0 || 2ull * lcap <= kCapLimit) &&
-                          ((hctl.overflow & 4u) == 0 || 2ull * ccap <= kCandLimit);
+                          ((hctl.overflow & 4u) == 0 || 2ull * ccap <= kCandLimit) &&
+                          ((hctl.overflow & 8u) == 0 || 2ull * scap <= kStackLimit);
     if (!can_grow || attempt >= c->max_retries) {
       *split = gn > 1;
-      return fail(GDIST_E_CAPACITY, "traversal storage exhausted (front %llu, leaf %llu, candidates %llu entries, %u queries)",
-                  (unsigned long long)fcap, (unsigned long long)lcap, (unsigned long long)ccap, gn);
+      return fail(GDIST_E_CAPACITY,
+                  "traversal storage exhausted (front %llu, leaf %llu, stack %llu, candidates %llu entries, %u queries)",
+                  (unsigned long long)fcap, (unsigned long long)lcap, (unsigned long long)scap,
+                  (unsigned long long)ccap, gn);
     }
     c->last.retries++;
     if (hctl.overflow & 1u) sf *= 2u;
     if (hctl.overflow & 2u) sl *= 2u;
     if (hctl.overflow & 4u) cps *= 2u;
+    if (hctl.overflow & 8u) scap *= 2u;
   }
   for (int i = 0; i < ST_N; ++i) {
     if (i == ST_PEAK) c->last_ctl_sum[i] = std::max(c->last_ctl_sum[i], hctl.stats[i]);
@@ -372,6 +385,7 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
   // start from the smaller group size.
   std::memset(&c->last_ctl_sum, 0, sizeof(c->last_ctl_sum));
   uint32_t group = (c->group_hint && c->group_hint < n) ? c->group_hint : n;
+  if (c->group_size && c->group_size < group) group = c->group_size;
   bool first_launch = true;
   for (uint32_t g0 = 0; g0 < n;) {
     const uint32_t gn = group < n - g0 ? group : n - g0;
@@ -457,7 +471,7 @@ gdist_status_t gdist_destroy(gdist_ctx_t c) {
   }
   c->meshes.clear();
   if (c->pinned) (void)hipHostFree(c->pinned);
-  DevBuf* bufs[] = {&c->refit_tab, &c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->counts, &c->cand,
+  DevBuf* bufs[] = {&c->refit_tab, &c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->stack, &c->counts, &c->cand,
                     &c->cand64, &c->ctl, &c->desc, &c->st, &c->res};
   for (DevBuf* b : bufs) release_buf(c, *b);
   for (int i = 0; i < 6; ++i)
@@ -480,8 +494,15 @@ gdist_status_t gdist_set_option(gdist_ctx_t c, const char* key, double v) {
   std::string k(key);
   if (k == "front_capacity") return u32opt(&c->front_cap, 64, 1u << 30);
   if (k == "leaf_capacity") return u32opt(&c->leaf_cap, 64, 1u << 30);
+  if (k == "stack_capacity") {
+    if (!(v >= 64.0 && v <= (double)kStackLimit) || v != std::floor(v))
+      return fail(GDIST_E_INVALID, "option stack_capacity=%g out of range [64, 2^31]", v);
+    c->stack_cap = (uint64_t)v;
+    return GDIST_OK;
+  }
   if (k == "cand_capacity") return u32opt(&c->cand_cap, 64, 1u << 30);
   if (k == "max_retries") return u32opt(&c->max_retries, 0, 32);
+  if (k == "group_size") return u32opt(&c->group_size, 0, 1u << 30);
   if (k == "expand_budget") return u32opt(&c->expand_budget, 4, 1u << 30);
   if (k == "k_cap") return u32opt(&c->k_cap, 1, 8);
   if (k == "bounds") return u32opt(&c->bounds, 0, 1);

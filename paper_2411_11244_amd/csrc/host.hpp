@@ -55,18 +55,20 @@ struct gdist_ctx {
   std::unordered_map<uint64_t, Mesh*> meshes;
   uint64_t next_handle = 1;
   // tunables
-  uint32_t front_cap = 1u << 24, leaf_cap = 1u << 24, cand_cap = 1u << 21;
+  uint32_t front_cap = 1u << 26, leaf_cap = 1u << 26, cand_cap = 1u << 21;
+  uint64_t stack_cap = 1ull << 26;
   uint32_t max_retries = 8, expand_budget = 1u << 18, k_cap = 5, blocks_per_cu = 0, bounds = 0;
   double kappa = 64.0;
   uint64_t memory_budget = 0, bytes_held = 0;
   // workspace
-  DevBuf ws_boxes, front[2], leaf[2], counts, cand, cand64, ctl, desc, st, res, refit_tab;
+  DevBuf ws_boxes, front[2], leaf[2], stack, counts, cand, cand64, ctl, desc, st, res, refit_tab;
   void* pinned = nullptr;       // host staging for descriptors and job tables
   size_t pinned_bytes = 0;
   uint32_t trav_blocks = 0, trav_threads = 0;
   int wall_khz = 0;
   bool trace = false;
   uint32_t group_hint = 0;                 // largest group of queries that fit one launch
+  uint32_t group_size = 0;                 // queries per traversal launch (0 = all)
   unsigned long long last_ctl_sum[gd::ST_N] = {};
   gdist_stats_t last{};
   bool busy = false;                       // a server owns the stream and workspace

@@ -59,14 +59,31 @@ enum StatIdx {
 };
 
 constexpr uint32_t kTraceRounds = 48;
+// A traversal workgroup appends at most its even share of a round's work items
+// plus kSegSlack (its waves' last, partial task group); segments are sized
+// from this so that the front and leaf-pair buffers cannot overflow.
+constexpr uint32_t kSegSlack = 4096;
+constexpr uint64_t kStackLimit = 1ull << 31;   // spill-stack entries (32 GiB)
+// Front entries expanded per round for segments of `seg` entries and nb
+// workgroups (each entry has at most 4 children when the round is large).
+inline uint32_t round_cap_for(uint32_t seg, uint32_t nb) {
+  uint64_t v = seg > kSegSlack ? (uint64_t)(seg - kSegSlack) * nb / 4u : 0u;
+  if (v > (1ull << 31)) v = 1ull << 31;
+  return v < 1u ? 1u : (uint32_t)v;
+}
+// Smallest segment that holds a round of `budget` work items beyond the
+// clamped minimum of one level per side.
+inline uint32_t min_segment(uint32_t budget, uint32_t nb) { return kSegSlack + 64u + budget / (nb ? nb : 1u); }
 
 // Control block of one persistent traversal launch.
 struct Ctl {
-  uint32_t overflow;       // bit 0 front, bit 1 leaf pairs, bit 2 candidates
+  uint32_t overflow;       // bit 0 front, bit 1 leaf pairs, bit 2 candidates, bit 3 spill stack
   uint32_t abort;          // a grid barrier timed out
   uint32_t bar_count;
   uint32_t bar_gen;
   uint32_t rounds_done;    // rounds completed by the latest launch
+  uint32_t stack_top[2];   // spill-stack height at the start of a round of parity i
+  uint32_t pad;
   unsigned long long stats[ST_N];
   // per-round device timestamps (constant-rate wall clock) and front sizes
   unsigned long long trace_t[kTraceRounds];
@@ -83,6 +100,9 @@ struct TravParams {
   uint4* leaf[2];          //   nblocks (the last) receives the root pairs of newly admitted queries
   uint32_t* fcount[2];     // entry count of every segment of front[i] (nblocks + 1 each)
   uint32_t* lcount[2];
+  uint4* stack;            // spill stack: front entries beyond round_cap wait here (LIFO)
+  uint32_t stack_cap;      // entries
+  uint32_t round_cap;      // most front entries expanded in one round (bounds every segment's output)
   Cand* cand;              // per-slot regions of cand_per_slot entries
   double* cand_d64;
   Ctl* ctl;

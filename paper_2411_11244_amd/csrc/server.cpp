@@ -3,8 +3,8 @@
 // A worker thread repeats one device step while queries are queued or in
 // flight:
 //   1. admission: queued queries take free slots while the shared traversal
-//      storage has room (the total live front after the last step stays below
-//      a quarter of its capacity) and the adaptive concurrency limit allows;
+//      storage has room (the live entries after the last step fill less than
+//      half of the spill stack) and the adaptive concurrency limit allows;
 //      each new slot gets its descriptor, the refit of its moving tree, its
 //      error window, greedy dive and root pair (through the admission segment);
 //   2. traversal: the persistent kernel runs at most rounds_per_step rounds of
@@ -13,11 +13,11 @@
 //   4. every slot with no live entries is complete: FP64 re-evaluation of its
 //      candidates, its result is copied back and queued for polling, and the
 //      slot is freed.
-// A front or leaf-pair overflow puts every query in flight back at the head of
-// the queue (keeping its submit time), clears the traversal storage and halves
-// the concurrency limit; when a query overflows alone the storage doubles (up
-// to 2^28 entries per buffer) before it runs again, and beyond that it fails
-// with E_CAPACITY.  A query whose candidate region fills up fails with
+// A spill-stack overflow puts every query in flight back at the head of the
+// queue (keeping its submit time), clears the traversal storage and halves the
+// concurrency limit; when a query overflows alone the stack doubles (up to
+// 2^31 entries) before it runs again, and beyond that it fails with
+// E_CAPACITY.  A query whose candidate region fills up fails with
 // E_CAPACITY once its traversal drains; the other queries are not affected.
 #include <atomic>
 #include <chrono>
@@ -54,9 +54,10 @@ struct gdist_server {
   gdist_ctx* c = nullptr;
   gdist_server_config_t cfg{};
   uint32_t S = 0, nb = 0, seg_f = 0, seg_l = 0, cps = 0;
+  uint64_t stack_cap = 0;
   size_t box_stride = 0;  // floats of refitted boxes per slot
   uint32_t max_leaves = 0;
-  DevBuf desc, st, res, boxes, front[2], leaf[2], counts, cand, cand64, ctl, live, list, tab;
+  DevBuf desc, st, res, boxes, front[2], leaf[2], stack, counts, cand, cand64, ctl, live, list, tab;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -94,6 +95,9 @@ TravParams params(gdist_server* sv) {
   p.fcount[1] = cnt + (sv->nb + 1);
   p.lcount[0] = cnt + 2 * (sv->nb + 1);
   p.lcount[1] = cnt + 3 * (sv->nb + 1);
+  p.stack = (uint4*)sv->stack.p;
+  p.stack_cap = (uint32_t)sv->stack_cap;
+  p.round_cap = round_cap_for(sv->seg_f < sv->seg_l ? sv->seg_f : sv->seg_l, sv->nb);
   p.cand = (Cand*)sv->cand.p;
   p.cand_d64 = (double*)sv->cand64.p;
   p.ctl = (Ctl*)sv->ctl.p;
@@ -117,24 +121,11 @@ size_t tab_offset(const gdist_server* sv) {
   return (sizeof(SlotDesc) * sv->S + 4ull * sv->S + 255) & ~(size_t)255;
 }
 
-// Double the front and leaf-pair buffers (all queries are out of flight).
+// Double the spill stack (all queries are out of flight).
 gdist_status_t grow_storage(gdist_server* sv) {
-  gdist_ctx* c = sv->c;
-  const uint64_t fcap = (uint64_t)sv->seg_f * (sv->nb + 1);
-  if (2 * fcap > kServerCapLimit) return GDIST_E_CAPACITY;
-  HIPCHK(hipStreamSynchronize(c->stream));
-  for (int b = 0; b < 2; ++b) {
-    release_buf(c, sv->front[b]);
-    release_buf(c, sv->leaf[b]);
-  }
-  sv->seg_f *= 2;
-  sv->seg_l = sv->seg_f;
-  gdist_status_t s = GDIST_OK;
-  for (int b = 0; b < 2 && s == GDIST_OK; ++b) {
-    s = ensure(c, sv->front[b], 32ull * fcap);
-    if (s == GDIST_OK) s = ensure(c, sv->leaf[b], 32ull * fcap);
-  }
-  return s;
+  if (2 * sv->stack_cap > kStackLimit) return GDIST_E_CAPACITY;
+  sv->stack_cap *= 2;
+  return ensure(sv->c, sv->stack, 16ull * sv->stack_cap);
 }
 
 void complete(gdist_server* sv, uint64_t tag, uint64_t t_submit, const gdist_result_t& r) {
@@ -225,7 +216,7 @@ gdist_status_t step(gdist_server* sv) {
   std::vector<Pending> reqs;
   {
     std::lock_guard<std::mutex> g(sv->mu);
-    const uint64_t room = (uint64_t)sv->seg_f * (sv->nb + 1) / 4;
+    const uint64_t room = sv->stack_cap / 2;
     while (!sv->pending.empty() && !sv->free_slots.empty() && sv->n_active + reqs.size() < sv->concurrency &&
            sv->live_total < room && reqs.size() < sv->free_slots.size()) {
       reqs.push_back(sv->pending.front());
@@ -254,8 +245,8 @@ gdist_status_t step(gdist_server* sv) {
     sv->stats.device_ms += ms;
   }
   if (hctl.abort) return fail(GDIST_E_DEVICE, "server step: grid barrier timed out");
-  if (hctl.overflow & 3u) {
-    // the fronts lost entries: every query in flight starts over later
+  if (hctl.overflow & 11u) {
+    // pending pairs were lost: every query in flight starts over later
     std::vector<uint32_t> act;
     for (uint32_t s = 0; s < sv->S; ++s)
       if (sv->active[s]) act.push_back(s);
@@ -369,8 +360,9 @@ void worker_main(gdist_server* sv) {
 
 void free_server(gdist_server* sv) {
   gdist_ctx* c = sv->c;
-  DevBuf* bufs[] = {&sv->desc, &sv->st,  &sv->res,    &sv->boxes, &sv->front[0], &sv->front[1], &sv->leaf[0],
-                    &sv->leaf[1], &sv->counts, &sv->cand, &sv->cand64, &sv->ctl,   &sv->live,     &sv->list, &sv->tab};
+  DevBuf* bufs[] = {&sv->desc,    &sv->st,     &sv->res,   &sv->boxes,  &sv->front[0], &sv->front[1],
+                    &sv->leaf[0], &sv->leaf[1], &sv->stack, &sv->counts, &sv->cand,     &sv->cand64,
+                    &sv->ctl,     &sv->live,    &sv->list,  &sv->tab};
   for (DevBuf* b : bufs) release_buf(c, *b);
   if (sv->pinned) (void)hipHostFree(sv->pinned);
   for (int i = 0; i < 2; ++i)
@@ -395,21 +387,24 @@ gdist_status_t gdist_server_start(gdist_ctx_t c, const gdist_server_config_t* co
   if (cf.max_slots == 0) cf.max_slots = 64;
   if (cf.rounds_per_step == 0) cf.rounds_per_step = 4;
   if (cf.front_capacity == 0) cf.front_capacity = 1ull << 25;
+  if (cf.stack_capacity == 0) cf.stack_capacity = 1ull << 26;
   if (cf.cand_per_slot == 0) cf.cand_per_slot = 1u << 17;
   if (cf.max_tris == 0)
     for (auto& kv : c->meshes) cf.max_tris = std::max(cf.max_tris, kv.second->n_tris);
   if (cf.max_slots > 512 || cf.max_tris == 0 || cf.front_capacity > kServerCapLimit ||
-      cf.cand_per_slot > (1u << 26)) {
+      cf.cand_per_slot > (1u << 26) || cf.stack_capacity > kStackLimit) {
     delete sv;
     return fail(GDIST_E_INVALID, "server config out of range (max_slots <= 512, a mesh or max_tris > 0, "
-                                 "front_capacity <= 2^28, cand_per_slot <= 2^26)");
+                                 "front_capacity <= 2^28, cand_per_slot <= 2^26, stack_capacity <= 2^31)");
   }
   sv->S = cf.max_slots;
   sv->nb = c->trav_blocks;
   sv->max_leaves = 1u << (31 - __builtin_clz(cf.max_tris));
   sv->box_stride = (12ull * sv->max_leaves + 63) & ~(size_t)63;
   sv->seg_f = (uint32_t)std::max<uint64_t>(cf.front_capacity / (sv->nb + 1), sv->S);
+  sv->seg_f = std::max(sv->seg_f, min_segment(c->expand_budget, sv->nb));
   sv->seg_l = sv->seg_f;
+  sv->stack_cap = cf.stack_capacity;
   sv->cps = cf.cand_per_slot;
   sv->concurrency = sv->S;
   const uint64_t fcap = (uint64_t)sv->seg_f * (sv->nb + 1);
@@ -425,6 +420,7 @@ gdist_status_t gdist_server_start(gdist_ctx_t c, const gdist_server_config_t* co
     A(sv->front[b], 16ull * fcap);
     A(sv->leaf[b], 16ull * fcap);
   }
+  A(sv->stack, 16ull * sv->stack_cap);
   A(sv->counts, 16ull * (sv->nb + 1));
   A(sv->cand, sizeof(Cand) * (size_t)sv->cps * sv->S);
   A(sv->cand64, sizeof(double) * (size_t)sv->cps * sv->S);

@@ -46,6 +46,7 @@ constexpr int kTravBlock = 768;                   // k_traverse: one 12-wave wor
 constexpr int kTravWaves = kTravBlock / kWave;
 constexpr uint32_t kQueue = 320;  // per-wave LDS queue of triangle pairs (63 + 4 x 64)
 constexpr int kRows = 4;          // expansion rows per wave iteration
+static_assert(kTravWaves * kRows * 64 + 256 <= (int)kSegSlack, "segment slack below one task group per wave");
 
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -353,7 +354,12 @@ struct Round {
   uint4* fout;
   const uint4* lin;
   uint4* lout;
+  uint4* stk;
   uint32_t nb, seg_f, seg_l;
+  uint32_t n_in;      // front entries expanded this round (the first n_in by global index)
+  uint32_t n_spill;   // front entries [n_in, n_in + n_spill) moved to the stack
+  uint32_t st;        // stack height at the round's start
+  uint32_t pop_base;  // stack entries [pop_base, st) are expanded after the front's
   bool lds_slots;
 };
 
@@ -470,11 +476,15 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
   for (int r = 0; r < R; ++r) {
     const uint64_t it = it0 + 64ull * r;
     act[r] = it < n_items;
-    // one wave-uniform search for the row's first entry, lanes step forward
+    // input entry ei: the front's first n_in entries, then popped stack
+    // entries; one wave-uniform search for the row's first front entry,
+    // lanes step forward
     const uint64_t rb = base0 + 64ull * r;
-    const uint32_t s0 = rb < n_items ? seg_find(bs->fpre, rd.nb, (uint32_t)(rb >> kk)) : 0u;
-    ent[r] = act[r] ? rd.fin[seg_addr_from(bs->fpre, rd.nb, rd.seg_f, s0, (uint32_t)(it >> kk))]
-                    : make_uint4(1u, 1u, 0u, 0u);
+    const uint32_t e0 = (uint32_t)(rb >> kk), ei = (uint32_t)(it >> kk);
+    const uint32_t s0 = (rb < n_items && e0 < rd.n_in) ? seg_find(bs->fpre, rd.nb, e0) : 0u;
+    ent[r] = !act[r]         ? make_uint4(1u, 1u, 0u, 0u)
+             : ei < rd.n_in ? rd.fin[seg_addr_from(bs->fpre, rd.nb, rd.seg_f, s0, ei)]
+                            : rd.stk[(uint64_t)rd.pop_base + (ei - rd.n_in)];
   }
   bool to_leaf[R], to_front[R];
   uint4 ne[R];
@@ -526,6 +536,15 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
   }
   append_rows<R>(to_leaf, ne, rd.lout, rd.seg_l, &bs->lo, &c->overflow, 2u, lane, lt);
   append_rows<R>(to_front, ne, rd.fout, rd.seg_f, &bs->fo, &c->overflow, 1u, lane, lt);
+}
+
+// Move front entries [n_in + base, n_in + base + 64) onto the spill stack
+// (one lane per entry).
+__device__ __forceinline__ void spill_wave(const BlockState* bs, const Round& rd, uint32_t base, uint32_t lane) {
+  const uint32_t s0 = seg_find(bs->fpre, rd.nb, rd.n_in + base);
+  const uint32_t j = base + lane;
+  if (j < rd.n_spill)
+    rd.stk[(uint64_t)rd.st + j] = rd.fin[seg_addr_from(bs->fpre, rd.nb, rd.seg_f, s0, rd.n_in + j)];
 }
 
 // Narrow phase, stage 1: one lane per leaf pair.  The lane loads the leaf
@@ -677,16 +696,33 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     rd.fout = p.front[(round + 1u) & 1u];
     rd.lin = p.leaf[round & 1u];
     rd.lout = p.leaf[(round + 1u) & 1u];
+    rd.stk = p.stack;
     if (lds_slots)
       for (uint32_t s = tid; s < p.n_slots; s += kTravBlock) bs->best[s] = ld_rlx(&p.st[s].best);
     block_prefix(p.fcount[round & 1u], rd.nb, bs->fpre, bs->scan);
     block_prefix(p.lcount[round & 1u], rd.nb, bs->lpre, bs->scan);
     const uint32_t n = bs->fpre[rd.nb];
     const uint32_t nl = bs->lpre[rd.nb];
-    if (n == 0u && nl == 0u) break;
+    // Bounded memory: at most round_cap front entries are expanded per round.
+    // A longer front moves its surplus onto the spill stack; a shorter one is
+    // topped up from the stack's top (the most recently spilled, i.e. deepest
+    // entries), so pending pairs are worked off depth-first in chunks.  Every
+    // workgroup derives the same decision from the same counts.
+    rd.st = ld_rlx(&c->stack_top[round & 1u]);
+    if (n == 0u && nl == 0u && rd.st == 0u) break;
+    rd.n_in = n < p.round_cap ? n : p.round_cap;
+    rd.n_spill = n - rd.n_in;
+    const uint32_t pop = rd.n_spill ? 0u : (rd.st < p.round_cap - rd.n_in ? rd.st : p.round_cap - rd.n_in);
+    rd.pop_base = rd.st - pop;
+    if ((uint64_t)rd.st + rd.n_spill > (uint64_t)p.stack_cap) {
+      if (blockIdx.x == 0 && tid == 0) atomicOr(&c->overflow, 8u);
+      break;
+    }
+    const uint32_t n_exp = rd.n_in + pop;
     if (blockIdx.x == 0 && tid == 0) {
       bs->stats[ST_ROUNDS] += 1ull;
-      if (n > bs->stats[ST_PEAK]) bs->stats[ST_PEAK] = n;
+      const unsigned long long live = (unsigned long long)n + rd.st;
+      if (live > bs->stats[ST_PEAK]) bs->stats[ST_PEAK] = live;
       if (r < kTraceRounds) {
         c->trace_t[r] = (unsigned long long)wall_clock64();
         c->trace_n[r] = n;
@@ -694,18 +730,20 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
       }
     }
     uint32_t k = p.k_cap;
-    while (k > 1u && ((uint64_t)n << (2u * k)) >= (uint64_t)p.expand_budget) --k;
+    while (k > 1u && ((uint64_t)n_exp << (2u * k)) >= (uint64_t)p.expand_budget) --k;
     const uint64_t leaf_items = (uint64_t)nl;   // one lane per leaf pair
     const uint64_t leaf_waves = (leaf_items + 63ull) >> 6;
-    const uint64_t exp_items = (uint64_t)n << (2u * k);
+    const uint64_t spill_end = leaf_waves + ((rd.n_spill + 63ull) >> 6);
+    const uint64_t exp_items = (uint64_t)n_exp << (2u * k);
     // expansion work is handed out in groups of kRows waves' worth of items
-    const uint64_t total = leaf_waves + ((exp_items + 64ull * kRows - 1ull) / (64ull * kRows));
+    const uint64_t total = spill_end + ((exp_items + 64ull * kRows - 1ull) / (64ull * kRows));
     uint32_t qn = 0;  // wave-uniform fill of this wave's LDS queue
     for (uint64_t w = gw;;) {
       const bool more = w < total;
       if (more) {
         if (w < leaf_waves) narrow_filter_wave(p, bs, rd, w * 64ull, leaf_items, lane, lt, q, qn, ws);
-        else expand_rows<kRows>(p, bs, rd, (w - leaf_waves) * 64ull * kRows, exp_items, k, lane, lt, ws);
+        else if (w < spill_end) spill_wave(bs, rd, (uint32_t)(w - leaf_waves) * 64u, lane);
+        else expand_rows<kRows>(p, bs, rd, (w - spill_end) * 64ull * kRows, exp_items, k, lane, lt, ws);
         w += nw;
       }
       while (qn >= 64u || (!more && qn > 0u)) {
@@ -726,6 +764,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
       if (blockIdx.x == 0) {
         p.fcount[(round + 1u) & 1u][gridDim.x] = 0u;   // admission segment consumed
         p.lcount[(round + 1u) & 1u][gridDim.x] = 0u;
+        st_rlx(&c->stack_top[(round + 1u) & 1u], rd.st + rd.n_spill - pop);
       }
       bs->fo = 0u;
       bs->lo = 0u;
@@ -866,9 +905,10 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_report(TravParams p, ui
   }
 }
 
-// Live entries per slot in the current front and leaf buffers (after a step):
-// workgroup b counts segment b of each (the last workgroup the admission
-// segment) in LDS and adds its non-zero counts to live[].
+// Live entries per slot in the current front and leaf buffers and on the
+// spill stack (after a step): workgroup b counts segment b of each (the last
+// workgroup the admission segment) and its grid-stride share of the stack in
+// LDS, and adds its non-zero counts to live[].
 __global__ __launch_bounds__(kTravThreads) void k_slot_hist(TravParams p, uint32_t* __restrict__ live) {
   __shared__ uint32_t h[kLdsSlots];
   for (uint32_t i = threadIdx.x; i < p.n_slots; i += kTravThreads) h[i] = 0u;
@@ -879,6 +919,9 @@ __global__ __launch_bounds__(kTravThreads) void k_slot_hist(TravParams p, uint32
   const uint4* ls = p.leaf[cur] + (uint64_t)b * p.seg_leaf;
   for (uint32_t i = threadIdx.x; i < nf; i += kTravThreads) atomicAdd(&h[fs[i].w], 1u);
   for (uint32_t i = threadIdx.x; i < nl; i += kTravThreads) atomicAdd(&h[ls[i].w], 1u);
+  const uint32_t ns = p.ctl->stack_top[cur];
+  for (uint32_t i = b * kTravThreads + threadIdx.x; i < ns; i += gridDim.x * kTravThreads)
+    atomicAdd(&h[p.stack[i].w], 1u);
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < p.n_slots; i += kTravThreads)
     if (h[i]) atomicAdd(&live[i], h[i]);

@@ -72,7 +72,8 @@ class gdist_stats_t(C.Structure):
 
 class gdist_server_config_t(C.Structure):
     _fields_ = [("max_slots", C.c_uint32), ("rounds_per_step", C.c_uint32), ("front_capacity", C.c_uint64),
-                ("cand_per_slot", C.c_uint32), ("max_tris", C.c_uint32)]
+                ("cand_per_slot", C.c_uint32), ("max_tris", C.c_uint32), ("reserved", C.c_uint32),
+                ("stack_capacity", C.c_uint64)]
 
 
 class gdist_completion_t(C.Structure):
@@ -286,8 +287,9 @@ def gdist_eval_tri_tri(ctx: int, p, q, mode: int = 0):
 
 # ------------------------------------------------------------------ serving
 def gdist_server_start(ctx: int, max_slots: int = 0, rounds_per_step: int = 0, front_capacity: int = 0,
-                       cand_per_slot: int = 0, max_tris: int = 0) -> int:
-    cfg = gdist_server_config_t(max_slots, rounds_per_step, front_capacity, cand_per_slot, max_tris)
+                       cand_per_slot: int = 0, max_tris: int = 0, stack_capacity: int = 0) -> int:
+    cfg = gdist_server_config_t(max_slots, rounds_per_step, front_capacity, cand_per_slot, max_tris, 0,
+                                stack_capacity)
     h = C.c_void_p()
     _check(lib().gdist_server_start(ctx, C.byref(cfg), C.byref(h)))
     return h.value

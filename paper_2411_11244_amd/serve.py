@@ -24,12 +24,13 @@ from . import gdist
 
 def run_stream(ctx: int, handles: Sequence[int], queries, max_slots: int = 64, rounds_per_step: int = 4,
                front_capacity: int = 0, cand_per_slot: int = 0, time_scale: float = 1.0,
-               timeout_s: float = 300.0) -> dict:
+               timeout_s: float = 300.0, stack_capacity: int = 0) -> dict:
     """Submit ``queries`` (meshgen.Query with .arrival seconds) at their arrival
     times (scaled by ``time_scale``; 0 submits everything at once) and collect
     every completion.  Returns {"results": [dict per query, in query order],
     "latency_ms": np.ndarray, "wall_s": float, "stats": server stats}."""
-    srv = gdist.gdist_server_start(ctx, max_slots, rounds_per_step, front_capacity, cand_per_slot)
+    srv = gdist.gdist_server_start(ctx, max_slots, rounds_per_step, front_capacity, cand_per_slot, 0,
+                                   stack_capacity)
     n = len(queries)
     results: List[dict] = [None] * n  # type: ignore
     got = 0

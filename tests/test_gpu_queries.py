@@ -173,27 +173,35 @@ def test_batch_equals_single(orc, gctx):
 
 
 def test_capacity_retry_gives_same_result(orc, gctx):
-    w = g.tiny(4)
-    m, q = w.meshes[0], w.queries[0]
+    """A torus against itself at the same pose touches everywhere, so its
+    fronts are large.  With rounds capped at 4,096 expanded entries (the
+    smallest segments) and a 64-entry spill stack the stack overflows; the
+    retries grow it and the result equals the unconstrained one.  With no
+    retries allowed the query fails with E_CAPACITY."""
+    m = g.torus(48, 24, 1.0, 0.3)
+    I = g.identity_pose()
     ctx = gdist.gdist_create(0)
     try:
         h = build(ctx, m)
-        r0 = gdist.gdist_query(ctx, h, h, q.pose_a, q.pose_b, 0)
-        for key in ("front_capacity", "leaf_capacity", "cand_capacity"):
-            gdist.gdist_set_option(ctx, key, 64)
-        gdist.gdist_set_option(ctx, "max_retries", 20)
-        r1 = gdist.gdist_query(ctx, h, h, q.pose_a, q.pose_b, 0)
+        r0 = gdist.gdist_query(ctx, h, h, I, I, 0)
+        assert r0["distance"] == 0.0 and r0["flags"] & gdist.GDIST_F_ZERO
+        for key, v in (("front_capacity", 64), ("leaf_capacity", 64), ("stack_capacity", 64),
+                       ("expand_budget", 4), ("max_retries", 20)):
+            gdist.gdist_set_option(ctx, key, v)
+        r1 = gdist.gdist_query(ctx, h, h, I, I, 0)
         st = gdist.gdist_last_stats(ctx)
         assert st["retries"] > 0
         assert r1["distance"] == r0["distance"]
         assert (r1["tri_a"], r1["tri_b"]) == (r0["tri_a"], r0["tri_b"])
+        assert r1["n_ties"] == r0["n_ties"]
         ctx2 = gdist.gdist_create(0)
         try:
             h2 = build(ctx2, m)
-            gdist.gdist_set_option(ctx2, "max_retries", 0)
-            gdist.gdist_set_option(ctx2, "front_capacity", 64)
+            for key, v in (("max_retries", 0), ("front_capacity", 64), ("stack_capacity", 64),
+                           ("expand_budget", 4)):
+                gdist.gdist_set_option(ctx2, key, v)
             with pytest.raises(gdist.GdistError) as ei:
-                gdist.gdist_query(ctx2, h2, h2, q.pose_a, q.pose_b, 0)
+                gdist.gdist_query(ctx2, h2, h2, I, I, 0)
             assert ei.value.status == gdist.GDIST_E_CAPACITY
         finally:
             gdist.gdist_destroy(ctx2)

@@ -69,11 +69,16 @@ def test_server_sample_vs_oracle(orc, gctx, served):
 
 
 def test_server_storage_growth(gctx, served):
-    """Front storage far too small: queries are requeued, the storage grows,
-    and every result still equals the result alone."""
+    """Front and spill stack far too small: rounds expand few entries, the
+    stack overflows, queries are requeued, the stack grows, and every result
+    still equals the result alone."""
     pool, handles, qs, alone = served
-    out = run_stream(gctx, handles, qs[:24], max_slots=16, rounds_per_step=2, front_capacity=4096,
-                     time_scale=0.0, timeout_s=120)
+    gdist.gdist_set_option(gctx, "expand_budget", 4)   # rounds of at most 4,096 entries
+    try:
+        out = run_stream(gctx, handles, qs[:24], max_slots=16, rounds_per_step=2, front_capacity=64,
+                         time_scale=0.0, timeout_s=120, stack_capacity=256)
+    finally:
+        gdist.gdist_set_option(gctx, "expand_budget", 1 << 18)
     for r, a in zip(out["results"], alone[:24]):
         _same(r, a)
     assert out["stats"]["requeued"] > 0
