@@ -44,7 +44,22 @@ def parse():
     ap.add_argument("--nu", type=int, default=2740)
     ap.add_argument("--nv", type=int, default=1369)
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2411_11244_amd", "tuning", "rings_mi355x.json"),
+                    help="launch options tuned for this workload ('' = library defaults)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the timed steps, run one elementwise copy reading and writing this many MiB "
+                         "(the scale for rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def traffic_record():
+    """HBM bytes per k_traverse launch from the committed rocprofv3 PMC summary,
+    or None when the kernel or its launch configuration changed since."""
+    from paper_2411_11244_amd import profsum
+    rec = profsum.read_record(os.path.join(ROOT, "profiles", "k_traverse_rings_traffic.md"))
+    if not rec or rec.get("sources_sha256") != profsum.sources_sha256():
+        return None
+    return rec
 
 
 def main():
@@ -64,6 +79,10 @@ def main():
     w = g.rings(frames=args.frames, nu=args.nu, nv=args.nv)
     mesh = w.meshes[0]
     ctx = gdist.gdist_create(0)
+    tuned = None
+    if args.tuning:
+        from paper_2411_11244_amd import tune
+        tuned = tune.apply(ctx, args.tuning).get("best")
     h = gdist.gdist_build(ctx, mesh.verts, mesh.tris)
     info = gdist.gdist_mesh_info(ctx, h)
     descs = [gdist.make_desc(h, h, q.pose_a, q.pose_b, gdist.GDIST_MIN) for q in w.queries]
@@ -81,6 +100,13 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     qps = args.frames * args.steps / (t1 - t0)
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib << 18
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- dominant kernel: k_traverse, timed by the library's HIP events
     # around each of its launches on the library's stream (the timed steps only)
@@ -89,8 +115,14 @@ def main():
     trav_bytes = sum(s["bytes_traversal"] + s["bytes_narrow"] for s in stats)
     avg_launch_ms = trav_ms / max(1, trav_launches)
     trav_gbs = trav_bytes / (trav_ms * 1e-3) / 1e9
+    pmc = traffic_record()
     roof = {"bound": "hbm", "kernel": "k_traverse", "achieved": round(trav_gbs, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(trav_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(trav_gbs / HBM_PEAK_GBS, 4),
+            "traffic": pmc["traffic_bytes_per_launch"] if pmc else None,
+            "traffic_gbs": round(pmc["traffic_bytes_per_launch"] / (avg_launch_ms * 1e-3) / 1e9, 1) if pmc else None,
+            "traffic_note": ("HBM bytes per launch, rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a copy kernel "
+                             "(profiles/k_traverse_rings_traffic.md)") if pmc else
+                            "null: no PMC summary for the current kernel sources and launch options",
             "algorithmic_bytes_per_launch": int(trav_bytes / max(1, trav_launches)),
             "avg_ms_per_launch": round(avg_launch_ms, 5), "launches": int(trav_launches),
             "bytes_per_unit": "16 B per entry popped + 48 B per child pair + 16 B per entry pushed; "
@@ -151,7 +183,8 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "rings", "tris_per_mesh": N, "frames_per_step": args.frames,
-                   "grid": [args.nu, args.nv], "mode": "min", "form": "batched (one launch per step)"},
+                   "grid": [args.nu, args.nv], "mode": "min", "form": "batched (one call per step)",
+                   "launch_options": tuned},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4),
                        "form": "plain (one query per launch)",

@@ -141,7 +141,7 @@ gdist_status_t gdist_destroy(gdist_ctx_t ctx);
  *                     most about a quarter of it, the surplus waits on the
  *                     spill stack
  *   "leaf_capacity"   leaf pairs per narrow-phase buffer (16 B each)
- *   "stack_capacity"  spill-stack entries (16 B each), initial value; doubles on
+ *   "stack_capacity"  spill-stack entries (16 B each), initial value (2^27); doubles on
  *                     overflow up to 2^31
  *   "cand_capacity"   FP64 candidates (24 B each)
  *   "max_retries"     capacity doublings before GDIST_E_CAPACITY

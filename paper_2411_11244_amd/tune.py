@@ -1,10 +1,13 @@
 """Autotuner for the traversal's launch parameters.
 
 Sweeps the adaptive-depth budget C ("expand_budget": k is the largest value
-with 4^k n < C), the per-round depth cap ("k_cap") and the persistent grid
-size ("blocks_per_cu") on a set of sample queries, and keeps the setting with
-the lowest median device time.  The choice never changes a result, only the
-amount of work per round and the number of rounds.
+with 4^k n < C), the per-round depth cap ("k_cap"), the persistent grid size
+("blocks_per_cu"), the front buffers ("front_capacity", which also bounds the
+entries a round expands; the leaf-pair buffers follow it) and the queries
+traversed per launch ("group_size") on a set of sample queries, and keeps the
+setting with the lowest median device time.  The choice never changes a
+result, only the amount of work per round, the number of rounds and the
+locality of the trees' boxes in the caches.
 
     python -m paper_2411_11244_amd.tune --out tune.json   (needs the GPU)
 
@@ -24,7 +27,13 @@ import numpy as np
 
 from . import gdist
 
-KEYS = ("expand_budget", "k_cap", "blocks_per_cu")
+KEYS = ("expand_budget", "k_cap", "blocks_per_cu", "front_capacity", "group_size")
+
+
+def _set(ctx: int, k: str, v) -> None:
+    gdist.gdist_set_option(ctx, k, float(v))
+    if k == "front_capacity":
+        gdist.gdist_set_option(ctx, "leaf_capacity", float(v))
 
 
 def apply(ctx: int, path_or_dict) -> Dict:
@@ -32,9 +41,10 @@ def apply(ctx: int, path_or_dict) -> Dict:
     if isinstance(path_or_dict, str):
         with open(path_or_dict) as f:
             cfg = json.load(f)
+    best = cfg.get("best", cfg)
     for k in KEYS:
-        if k in cfg.get("best", cfg):
-            gdist.gdist_set_option(ctx, k, float(cfg.get("best", cfg)[k]))
+        if k in best:
+            _set(ctx, k, best[k])
     return cfg
 
 
@@ -54,20 +64,20 @@ def tune(ctx: int, descs: List, grid: Dict[str, Iterable], reps: int = 3, log=pr
     for values in itertools.product(*(grid[n] for n in names)):
         setting = dict(zip(names, values))
         for k, v in setting.items():
-            gdist.gdist_set_option(ctx, k, float(v))
+            _set(ctx, k, v)
         ms = time_setting(ctx, descs, reps)
         results.append({**setting, "ms": ms})
         log(f"tune {setting} -> {ms:.4f} ms")
     best = min(results, key=lambda r: r["ms"])
     for k in names:
-        gdist.gdist_set_option(ctx, k, float(best[k]))
+        _set(ctx, k, best[k])
     return {"best": {k: best[k] for k in names}, "ms": best["ms"], "results": results}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="rings", choices=["rings", "tiny"])
-    ap.add_argument("--frames", type=int, default=4)
+    ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--out", default="")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
@@ -83,7 +93,8 @@ def main():
     ctx = gdist.gdist_create(0)
     hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in w.meshes]
     descs = [gdist.make_desc(hs[q.a], hs[q.b], q.pose_a, q.pose_b, q.mode) for q in w.queries]
-    grid = {"expand_budget": [1 << 16, 1 << 18, 1 << 20, 1 << 22], "k_cap": [3, 5], "blocks_per_cu": [0]}
+    grid = {"expand_budget": [1 << 18, 1 << 20], "k_cap": [5], "blocks_per_cu": [0],
+            "front_capacity": [1 << 26, 1 << 27], "group_size": [0, 25, 12, 8]}
     t = time.time()
     res = tune(ctx, descs, grid, args.reps)
     res["workload"] = args.workload
