@@ -87,23 +87,31 @@ __device__ __forceinline__ void load_tri_xf(const float* __restrict__ tris, uint
 // --------------------------------------------------------------------------
 __device__ __forceinline__ float sq(float x) { return x * x; }
 
-// Min-distance bounds of two boxes: `lower` = conventional d_min^L,
-// `upper` = enhanced d_min^U (or, if !enhanced, the conventional upper bound
-// d_max^U, the distance between the farthest points of the boxes).
-__device__ __forceinline__ void bounds_min(const Box& a, const Box& b, bool enhanced, float& lower,
-                                           float& upper) {
-  float F[3], G[3], H[3], E[3], sgap = 0.f;
+// The bounds come in two parts: the cull bound (conventional d_min^L for the
+// minimum, conventional d_max^U for the maximum), needed for every pair, and
+// the improving bound (enhanced d_min^U, resp. enhanced d_max^L), which can
+// only help when the cull bound already beats the running best.  Each part
+// is a sum of non-negative per-axis squares, so no subtraction cancels.
+
+// Conventional d_min^L: the gap between the boxes.
+__device__ __forceinline__ float min_lower(const Box& a, const Box& b) {
+  float sgap = 0.f;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     float gap = fmaxf(0.f, fmaxf(b.lo[i] - a.hi[i], a.lo[i] - b.hi[i]));
     sgap += gap * gap;
-    F[i] = sq(fmaxf(b.hi[i] - a.lo[i], a.hi[i] - b.lo[i]));   // farthest, full intervals
   }
-  lower = sqrtf(sgap);
-  if (!enhanced) {
-    upper = sqrtf(F[0] + F[1] + F[2]);
-    return;
-  }
+  return sqrtf(sgap);
+}
+
+// Enhanced d_min^U (Sec. 4): the smallest, over the 36 pairs of a face of A
+// and a face of B, of the largest distance between the two faces; or, if
+// !enhanced, the conventional upper bound d_max^U (farthest corners).
+__device__ __forceinline__ float min_upper(const Box& a, const Box& b, bool enhanced) {
+  float F[3], G[3], H[3], E[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) F[i] = sq(fmaxf(b.hi[i] - a.lo[i], a.hi[i] - b.lo[i]));   // full intervals
+  if (!enhanced) return sqrtf(F[0] + F[1] + F[2]);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     // A's face flat on axis i at a in {lo, hi} against B's full interval
@@ -125,26 +133,37 @@ __device__ __forceinline__ void bounds_min(const Box& a, const Box& b, bool enha
   m = fminf(m, E[0] + (F[1] + F[2]));
   m = fminf(m, E[1] + (F[0] + F[2]));
   m = fminf(m, E[2] + (F[0] + F[1]));
-  upper = sqrtf(m);
+  return sqrtf(m);
 }
 
-// Max-distance bounds: `upper` = conventional d_max^U, `lower` = enhanced
-// d_max^L (or, if !enhanced, the conventional d_min^L).
-__device__ __forceinline__ void bounds_max(const Box& a, const Box& b, bool enhanced, float& upper,
-                                           float& lower) {
-  float Gp[3], F = 0.f, A2[3], B2[3], E[3], sgap = 0.f;
+// Min-distance bounds of two boxes: `lower` = conventional d_min^L,
+// `upper` = enhanced d_min^U (or, if !enhanced, the conventional upper bound
+// d_max^U, the distance between the farthest points of the boxes).
+__device__ __forceinline__ void bounds_min(const Box& a, const Box& b, bool enhanced, float& lower,
+                                           float& upper) {
+  lower = min_lower(a, b);
+  upper = min_upper(a, b, enhanced);
+}
+
+// Conventional d_max^U: the distance between the farthest corners.
+__device__ __forceinline__ float max_upper(const Box& a, const Box& b) {
+  float F = 0.f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) F += sq(fmaxf(b.hi[i] - a.lo[i], a.hi[i] - b.lo[i]));
+  return sqrtf(F);
+}
+
+// Enhanced d_max^L (Sec. 4, the mirror image for the maximum): the largest,
+// over the 36 face pairs, of the smallest distance between the two faces; or,
+// if !enhanced, the conventional lower bound d_min^L.
+__device__ __forceinline__ float max_lower(const Box& a, const Box& b, bool enhanced) {
+  float Gp[3], A2[3], B2[3], E[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     float gap = fmaxf(0.f, fmaxf(b.lo[i] - a.hi[i], a.lo[i] - b.hi[i]));
     Gp[i] = gap * gap;
-    sgap += Gp[i];
-    F += sq(fmaxf(b.hi[i] - a.lo[i], a.hi[i] - b.lo[i]));
   }
-  upper = sqrtf(F);
-  if (!enhanced) {
-    lower = sqrtf(sgap);
-    return;
-  }
+  if (!enhanced) return sqrtf(Gp[0] + Gp[1] + Gp[2]);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     // point a (a face of A flat on axis i) against B's interval: its gap
@@ -164,7 +183,15 @@ __device__ __forceinline__ void bounds_max(const Box& a, const Box& b, bool enha
   m = fmaxf(m, E[0] + (Gp[1] + Gp[2]));
   m = fmaxf(m, E[1] + (Gp[0] + Gp[2]));
   m = fmaxf(m, E[2] + (Gp[0] + Gp[1]));
-  lower = sqrtf(m);
+  return sqrtf(m);
+}
+
+// Max-distance bounds: `upper` = conventional d_max^U, `lower` = enhanced
+// d_max^L (or, if !enhanced, the conventional d_min^L).
+__device__ __forceinline__ void bounds_max(const Box& a, const Box& b, bool enhanced, float& upper,
+                                           float& lower) {
+  upper = max_upper(a, b);
+  lower = max_lower(a, b, enhanced);
 }
 
 // --------------------------------------------------------------------------

@@ -62,13 +62,14 @@ constexpr uint32_t kTraceRounds = 48;
 // A traversal workgroup appends at most its even share of a round's work items
 // plus kSegSlack (its waves' last, partial task group); segments are sized
 // from this so that the front and leaf-pair buffers cannot overflow.
-constexpr uint32_t kSegSlack = 4096;
+constexpr uint32_t kSegSlack = 8192;
 constexpr uint64_t kStackLimit = 1ull << 31;   // spill-stack entries (32 GiB)
 // Front entries expanded per round for segments of `seg` entries and nb
 // workgroups (each entry has at most 4 children when the round is large).
+// At most 2^29, so a round's work items (4 per entry) stay below 2^31.
 inline uint32_t round_cap_for(uint32_t seg, uint32_t nb) {
   uint64_t v = seg > kSegSlack ? (uint64_t)(seg - kSegSlack) * nb / 4u : 0u;
-  if (v > (1ull << 31)) v = 1ull << 31;
+  if (v > (1ull << 29)) v = 1ull << 29;
   return v < 1u ? 1u : (uint32_t)v;
 }
 // Smallest segment that holds a round of `budget` work items beyond the

@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
 // loop issues no global atomics; at the round's end each workgroup publishes
 // its counts, and the next round maps a global entry index to (segment,
 // offset) through an exclusive prefix sum over the workgroups' counts.
-constexpr uint32_t kMaxBlocks = 1024;
+constexpr uint32_t kMaxBlocks = 1023;   // segments (+ admission) fit the 1024-point search
 constexpr uint32_t kLdsSlots = 512;
 
 struct BlockState {
@@ -381,24 +381,74 @@ __device__ __forceinline__ void improve_best(const TravParams& p, BlockState* bs
   }
 }
 
-// Largest segment s with pre[s] <= e (binary search; called with a
-// wave-uniform e, so every lane reads the same LDS words).
-__device__ __forceinline__ uint32_t seg_find(const uint32_t* pre, uint32_t nb, uint32_t e) {
-  uint32_t lo = 0, hi = nb;
-  while (hi - lo > 1u) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (pre[mid] <= e) lo = mid;
-    else hi = mid;
-  }
-  return lo;
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Largest segment s < nb with pre[s] <= e, for a wave-uniform e < pre[nb]
+// (pre is non-decreasing, pre[0] = 0, nb <= 1024).  Two parallel LDS probes
+// and ballots instead of a dependent binary search: 64 coarse points 16
+// segments apart, then the 16 segments after the last coarse point <= e.
+// Needs the whole wave active.
+__device__ __forceinline__ uint32_t seg_find_wave(const uint32_t* pre, uint32_t nb, uint32_t e, uint32_t lane) {
+  const uint32_t ci = lane << 4;
+  const uint32_t c = (uint32_t)__popcll(__ballot(ci < nb && pre[ci] <= e)) - 1u;
+  const uint32_t fi = (c << 4) + (lane & 15u);
+  const uint32_t f = (uint32_t)__popcll(__ballot(lane < 16u && fi < nb && pre[fi] <= e)) - 1u;
+  return (c << 4) + f;
 }
 // Address s*seg + e - pre[s] of entry e >= pre[s0], stepping forward from the
-// segment s0 of the row's first entry (a row rarely crosses a segment end).
+// segment s0 of the row's first entry (used when a row crosses a segment end).
 __device__ __forceinline__ uint32_t seg_addr_from(const uint32_t* pre, uint32_t nb, uint32_t seg, uint32_t s0,
                                                   uint32_t e) {
   uint32_t s = s0;
   while (s + 1u < nb && pre[s + 1u] <= e) ++s;
   return s * seg + (e - pre[s]);
+}
+// Address of entry e of a row whose entries span [e_first, e_last] (both
+// wave-uniform, e_last < pre[nb]); the row usually lies in one segment.
+__device__ __forceinline__ uint32_t row_addr(const uint32_t* pre, uint32_t nb, uint32_t seg, uint32_t e_first,
+                                            uint32_t e_last, uint32_t e, uint32_t lane) {
+  const uint32_t s0 = seg_find_wave(pre, nb, e_first, lane);
+  if (pre[s0 + 1u] > e_last) return s0 * seg + (e - pre[s0]);
+  return seg_addr_from(pre, nb, seg, s0, e);
+}
+
+// Per-query values a lane needs, read once per row: from scalar loads when the
+// row's active lanes all belong to one query (the common case: segments hold
+// runs of one query's entries), else per lane.
+struct SlotView {
+  const float* boxA;
+  const float* boxB;
+  const float* trisA;
+  const float* trisB;
+  uint32_t mode, depthA, depthB, LA, LB, nA, nB, enh;
+  float delta, best;
+};
+__device__ __forceinline__ void fill_view(const TravParams& p, const BlockState* bs, bool lds, uint32_t slot,
+                                          SlotView& v) {
+  const SlotDesc& d = p.desc[slot];
+  v.boxA = d.boxA;
+  v.boxB = d.boxB;
+  v.trisA = d.trisA;
+  v.trisB = d.trisB;
+  v.mode = d.mode;
+  v.depthA = d.depthA;
+  v.depthB = d.depthB;
+  v.LA = d.LA;
+  v.LB = d.LB;
+  v.nA = d.nA;
+  v.nB = d.nB;
+  v.enh = d.enhanced;
+  v.delta = get_delta(p, bs, lds, slot);
+  v.best = get_best(p, bs, lds, slot);
+}
+// `act` lanes' slots; lane 0 must be active whenever any lane is.
+__device__ __forceinline__ SlotView slot_view(const TravParams& p, const BlockState* bs, bool lds, bool act,
+                                              uint32_t slot) {
+  SlotView v;
+  const uint32_t s_u = wave_uniform(slot);
+  if (__ballot(act && slot != s_u) == 0ull) fill_view(p, bs, lds, s_u, v);
+  else fill_view(p, bs, lds, slot, v);
+  return v;
 }
 
 // Exclusive prefix over nb <= 4 * kTravBlock counts; pre[nb] = total.
@@ -461,46 +511,50 @@ __device__ __forceinline__ void append_rows(const bool* take, const uint4* e, ui
   }
 }
 
-// Expansion of R consecutive waves' worth of items of the current front
-// (items it0 + 64 r + lane).  All loads of the R rows are issued before any
-// result is needed, and the survivors of the R rows are appended together.
+// Expansion of R consecutive waves' worth of items of the current round's
+// input (items it0 + 64 r + lane; item t is child t & (4^k - 1) of input
+// entry t >> 2k).  All entry loads of the R rows are issued before any result
+// is needed, and the survivors of the R rows are appended together.  Row
+// starts and bounds are wave-uniform.
 template <int R>
-__device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs, const Round& rd, uint64_t base0,
-                                            uint64_t n_items, uint32_t k, uint32_t lane, uint64_t lt, WaveStats& ws) {
-  const uint64_t it0 = base0 + lane;
+__device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base0,
+                                            uint32_t n_items, uint32_t kk, uint32_t lane, uint64_t lt, WaveStats& ws) {
   Ctl* c = p.ctl;
-  const uint32_t kk = 2 * k;
   uint4 ent[R];
   bool act[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const uint64_t it = it0 + 64ull * r;
+    const uint32_t rb = base0 + 64u * r;
+    const uint32_t it = rb + lane;
     act[r] = it < n_items;
-    // input entry ei: the front's first n_in entries, then popped stack
-    // entries; one wave-uniform search for the row's first front entry,
-    // lanes step forward
-    const uint64_t rb = base0 + 64ull * r;
-    const uint32_t e0 = (uint32_t)(rb >> kk), ei = (uint32_t)(it >> kk);
-    const uint32_t s0 = (rb < n_items && e0 < rd.n_in) ? seg_find(bs->fpre, rd.nb, e0) : 0u;
-    ent[r] = !act[r]         ? make_uint4(1u, 1u, 0u, 0u)
-             : ei < rd.n_in ? rd.fin[seg_addr_from(bs->fpre, rd.nb, rd.seg_f, s0, ei)]
-                            : rd.stk[(uint64_t)rd.pop_base + (ei - rd.n_in)];
+    ent[r] = make_uint4(1u, 1u, 0u, 0u);
+    if (rb < n_items) {
+      // input entry ei: the front's first n_in entries, then popped stack entries
+      const uint32_t ei = it >> kk, e0 = rb >> kk;
+      const uint32_t elast = ((n_items - 1u < rb + 63u ? n_items - 1u : rb + 63u) >> kk);
+      if (e0 < rd.n_in) {
+        const uint32_t fend = elast < rd.n_in ? elast : rd.n_in - 1u;
+        const uint32_t addr = row_addr(bs->fpre, rd.nb, rd.seg_f, e0, fend, ei < rd.n_in ? ei : fend, lane);
+        if (act[r]) ent[r] = ei < rd.n_in ? rd.fin[addr] : rd.stk[(uint64_t)rd.pop_base + (ei - rd.n_in)];
+      } else if (act[r]) {
+        ent[r] = rd.stk[(uint64_t)rd.pop_base + (ei - rd.n_in)];
+      }
+    }
   }
   bool to_leaf[R], to_front[R];
   uint4 ne[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const uint64_t it = it0 + 64ull * r;
-    const uint32_t sub = (uint32_t)(it & ((1ull << kk) - 1ull));
+    const uint32_t it = base0 + 64u * r + lane;
+    const uint32_t sub = it & ((1u << kk) - 1u);
     const uint32_t slot = ent[r].w;
-    const SlotDesc* d = p.desc + slot;
-    const uint32_t mode = d->mode;
-    const float delta = get_delta(p, bs, rd.lds_slots, slot);
-    const float best = get_best(p, bs, rd.lds_slots, slot);
+    const SlotView v = slot_view(p, bs, rd.lds_slots, act[r], slot);
+    const uint32_t mode = v.mode;
+    const float delta = v.delta, best = v.best;
     const float key = bitsf(ent[r].z);
     bool a = act[r] && (mode == 0 ? !(key - delta > best) : !(key + delta < best));
     uint32_t kA, kB;
-    split_levels(d->depthA - level_of(ent[r].x), d->depthB - level_of(ent[r].y), kk, kA, kB);
+    split_levels(v.depthA - level_of(ent[r].x), v.depthB - level_of(ent[r].y), kk, kA, kB);
     a = a && (sub >> (kA + kB)) == 0u;
     add_stat(ws, ST_POPPED, a && sub == 0u);
     add_stat(ws, ST_CHILD, a);
@@ -509,23 +563,19 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
     bool keep = false;
     float improve = 0.f, nkey = 0.f;
     if (a) {
-      Box ba = load_box(d->boxA, ca), bb = load_box(d->boxB, cb);
-      const bool enh = d->enhanced != 0;
+      const Box ba = load_box(v.boxA, ca), bb = load_box(v.boxB, cb);
+      const bool enh = v.enh != 0;
       if (mode == 0) {
-        float lo, up;
-        bounds_min(ba, bb, enh, lo, up);
-        keep = lo - delta <= best;
-        improve = up + delta;
-        nkey = lo;
+        nkey = min_lower(ba, bb);
+        keep = nkey - delta <= best;
+        improve = min_upper(ba, bb, enh) + delta;
       } else {
-        float up, lo;
-        bounds_max(ba, bb, enh, up, lo);
-        keep = up + delta >= best;
-        improve = fmaxf(lo - delta, 0.f);
-        nkey = up;
+        nkey = max_upper(ba, bb);
+        keep = nkey + delta >= best;
+        improve = fmaxf(max_lower(ba, bb, enh) - delta, 0.f);
       }
     }
-    const bool isleaf = (ca >= d->LA) && (cb >= d->LB);
+    const bool isleaf = (ca >= v.LA) && (cb >= v.LB);
     ne[r] = make_uint4(ca, cb, fbits(nkey), slot);
     to_leaf[r] = a && keep && isleaf;
     to_front[r] = a && keep && !isleaf;
@@ -541,50 +591,52 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
 // Move front entries [n_in + base, n_in + base + 64) onto the spill stack
 // (one lane per entry).
 __device__ __forceinline__ void spill_wave(const BlockState* bs, const Round& rd, uint32_t base, uint32_t lane) {
-  const uint32_t s0 = seg_find(bs->fpre, rd.nb, rd.n_in + base);
   const uint32_t j = base + lane;
-  if (j < rd.n_spill)
-    rd.stk[(uint64_t)rd.st + j] = rd.fin[seg_addr_from(bs->fpre, rd.nb, rd.seg_f, s0, rd.n_in + j)];
+  const uint32_t jl = (rd.n_spill - 1u < base + 63u ? rd.n_spill - 1u : base + 63u);
+  const uint32_t addr =
+      row_addr(bs->fpre, rd.nb, rd.seg_f, rd.n_in + base, rd.n_in + jl, rd.n_in + (j < rd.n_spill ? j : jl), lane);
+  if (j < rd.n_spill) rd.stk[(uint64_t)rd.st + j] = rd.fin[addr];
 }
 
 // Narrow phase, stage 1: one lane per leaf pair.  The lane loads the leaf
 // pair's 1-2 triangles of each side once, gives each of the (up to 4)
 // triangle pairs the cheap separating-axis test, and pushes the survivors
 // onto the wave's LDS queue (at most 4 x 64 per call).
-__device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockState* bs, const Round& rd, uint64_t base,
-                                                   uint64_t n_items, uint32_t lane, uint64_t lt, uint4* q,
+__device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base,
+                                                   uint32_t n_items, uint32_t lane, uint64_t lt, uint4* q,
                                                    uint32_t& qn, WaveStats& ws) {
-  const uint64_t it = base + lane;
+  const uint32_t it = base + lane;
   bool act = it < n_items;
   uint4 ent = make_uint4(1u, 1u, 0u, 0u);
-  const uint32_t s0 = base < n_items ? seg_find(bs->lpre, rd.nb, (uint32_t)base) : 0u;
-  if (act) ent = rd.lin[seg_addr_from(bs->lpre, rd.nb, rd.seg_l, s0, (uint32_t)it)];
+  const uint32_t il = n_items - 1u < base + 63u ? n_items - 1u : base + 63u;
+  const uint32_t addr = row_addr(bs->lpre, rd.nb, rd.seg_l, base, il, act ? it : il, lane);
+  if (act) ent = rd.lin[addr];
   const uint32_t slot = ent.w;
-  const SlotDesc* d = p.desc + slot;
-  const uint32_t mode = d->mode;
-  const float delta = get_delta(p, bs, rd.lds_slots, slot);
-  const float best = get_best(p, bs, rd.lds_slots, slot);
+  const SlotView v = slot_view(p, bs, rd.lds_slots, act, slot);
+  const uint32_t mode = v.mode;
+  const float delta = v.delta, best = v.best;
   const float key = bitsf(ent.z);
   if (act) act = mode == 0 ? !(key - delta > best) : !(key + delta < best);
   add_stat(ws, ST_LEAF, act);
   uint32_t sa = 0, ea = 0, sb = 0, eb = 0;
   if (act) {
-    leaf_range(ent.x, d->depthA, d->nA, sa, ea);
-    leaf_range(ent.y, d->depthB, d->nB, sb, eb);
+    leaf_range(ent.x, v.depthA, v.nA, sa, ea);
+    leaf_range(ent.y, v.depthB, v.nB, sb, eb);
   }
   V3<float> P[2][3], Q[2][3];
   if (act && mode == 0) {
+    const Xf32& T = p.desc[slot].T;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       float a[9], b[9];
       const uint32_t ia = sa + i < ea ? sa + i : sa;
       const uint32_t ib = sb + i < eb ? sb + i : sb;
-      load_tri(d->trisA, ia, a);
-      load_tri_xf(d->trisB, ib, d->T, b);
+      load_tri(v.trisA, ia, a);
+      load_tri_xf(v.trisB, ib, T, b);
 #pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        P[i][v] = mk<float>(a[3 * v], a[3 * v + 1], a[3 * v + 2]);
-        Q[i][v] = mk<float>(b[3 * v], b[3 * v + 1], b[3 * v + 2]);
+      for (int w = 0; w < 3; ++w) {
+        P[i][w] = mk<float>(a[3 * w], a[3 * w + 1], a[3 * w + 2]);
+        Q[i][w] = mk<float>(b[3 * w], b[3 * w + 1], b[3 * w + 2]);
       }
     }
   }
@@ -607,17 +659,26 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
                                             uint32_t lane, uint64_t lt, WaveStats& ws) {
   Ctl* c = p.ctl;
   const uint32_t slot = e.x, pa = e.y, pb = e.z;
-  const SlotDesc* d = p.desc + slot;
-  const uint32_t mode = d->mode;
-  const float delta = get_delta(p, bs, lds, slot);
+  const SlotView v = slot_view(p, bs, lds, act, slot);
+  const uint32_t mode = v.mode;
+  const float delta = v.delta;
   float dd = 0.f, improve = 0.f;
   bool cand = false;
   if (act) {
     V3<float> P[3], Q[3];
-    load_pair(d, pa, pb, P, Q);
+    {
+      float a[9], b[9];
+      load_tri(v.trisA, pa, a);
+      load_tri_xf(v.trisB, pb, p.desc[slot].T, b);
+#pragma unroll
+      for (int w = 0; w < 3; ++w) {
+        P[w] = mk<float>(a[3 * w], a[3 * w + 1], a[3 * w + 2]);
+        Q[w] = mk<float>(b[3 * w], b[3 * w + 1], b[3 * w + 2]);
+      }
+    }
     dd = sqrtf(mode == 0 ? tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr)
                          : tri_tri_max_d2<float, false>(P, Q, nullptr, nullptr));
-    const float best = get_best(p, bs, lds, slot);
+    const float best = v.best;
     if (mode == 0) {
       improve = dd + delta;
       cand = dd - delta <= best;
@@ -668,9 +729,9 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
   const uint64_t lt = (1ull << lane) - 1ull;
-  const uint32_t wib = tid >> 6;
-  const uint64_t gw = (uint64_t)blockIdx.x * kTravWaves + wib;
-  const uint64_t nw = (uint64_t)gridDim.x * kTravWaves;
+  const uint32_t wib = wave_uniform(tid >> 6);
+  const uint32_t gw = blockIdx.x * kTravWaves + wib;
+  const uint32_t nw = gridDim.x * kTravWaves;
   uint4* q = sq[wib];
   const bool lds_slots = p.n_slots <= kLdsSlots;
   WaveStats ws;
@@ -729,21 +790,23 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
         c->trace_nl[r] = nl;
       }
     }
+    // k: the largest value with 4^k n < C, clamped to [1, k_cap] (Sec. 5);
+    // item counts stay below 2^32 (the host bounds round_cap and C)
     uint32_t k = p.k_cap;
     while (k > 1u && ((uint64_t)n_exp << (2u * k)) >= (uint64_t)p.expand_budget) --k;
-    const uint64_t leaf_items = (uint64_t)nl;   // one lane per leaf pair
-    const uint64_t leaf_waves = (leaf_items + 63ull) >> 6;
-    const uint64_t spill_end = leaf_waves + ((rd.n_spill + 63ull) >> 6);
-    const uint64_t exp_items = (uint64_t)n_exp << (2u * k);
+    const uint32_t kk = 2u * k;
+    const uint32_t leaf_waves = (nl + 63u) >> 6;   // one lane per leaf pair
+    const uint32_t spill_end = leaf_waves + ((rd.n_spill + 63u) >> 6);
+    const uint32_t exp_items = n_exp << kk;
     // expansion work is handed out in groups of kRows waves' worth of items
-    const uint64_t total = spill_end + ((exp_items + 64ull * kRows - 1ull) / (64ull * kRows));
+    const uint32_t total = spill_end + (uint32_t)(((uint64_t)exp_items + 64u * kRows - 1u) / (64u * kRows));
     uint32_t qn = 0;  // wave-uniform fill of this wave's LDS queue
-    for (uint64_t w = gw;;) {
+    for (uint32_t w = gw;;) {
       const bool more = w < total;
       if (more) {
-        if (w < leaf_waves) narrow_filter_wave(p, bs, rd, w * 64ull, leaf_items, lane, lt, q, qn, ws);
-        else if (w < spill_end) spill_wave(bs, rd, (uint32_t)(w - leaf_waves) * 64u, lane);
-        else expand_rows<kRows>(p, bs, rd, (w - spill_end) * 64ull * kRows, exp_items, k, lane, lt, ws);
+        if (w < leaf_waves) narrow_filter_wave(p, bs, rd, w * 64u, nl, lane, lt, q, qn, ws);
+        else if (w < spill_end) spill_wave(bs, rd, (w - leaf_waves) * 64u, lane);
+        else expand_rows<kRows>(p, bs, rd, (w - spill_end) * 64u * kRows, exp_items, kk, lane, lt, ws);
         w += nw;
       }
       while (qn >= 64u || (!more && qn > 0u)) {
