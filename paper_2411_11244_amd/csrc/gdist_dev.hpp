@@ -28,9 +28,20 @@ struct Box {
   float lo[3], hi[3];
 };
 
+// Mesh data always lives in device global memory; pointers read from
+// descriptors are generic to the compiler, so loads through them would be
+// flat accesses (which also hold the LDS wait counter).  Casting to the global
+// address space keeps them plain global loads.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)(p);
+}
+
+typedef float f2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ Box load_box(const float* __restrict__ boxes, uint32_t node) {
-  const float2* p = reinterpret_cast<const float2*>(boxes + 6ull * node);
-  float2 u = p[0], v = p[1], w = p[2];
+  const __attribute__((address_space(1))) f2v* p =
+      reinterpret_cast<const __attribute__((address_space(1))) f2v*>(gptr(boxes) + 6ull * node);
+  const f2v u = p[0], v = p[1], w = p[2];
   Box r;
   r.lo[0] = u.x; r.lo[1] = u.y; r.lo[2] = v.x;
   r.hi[0] = v.y; r.hi[1] = w.x; r.hi[2] = w.y;
@@ -70,7 +81,7 @@ __device__ __forceinline__ void xform(const Xf32& T, float x, float y, float z, 
 
 // Load triangle `pos` (9 floats, leaf order) and optionally transform it.
 __device__ __forceinline__ void load_tri(const float* __restrict__ tris, uint32_t pos, float* o) {
-  const float* p = tris + 9ull * pos;
+  const __attribute__((address_space(1))) float* p = gptr(tris) + 9ull * pos;
 #pragma unroll
   for (int k = 0; k < 9; ++k) o[k] = p[k];
 }
@@ -398,15 +409,34 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Wave-wide min / max (the whole wave active): DPP exchanges inside each row
+// of 16 lanes (quad swaps, then half-row and row mirrors leave every lane with
+// its row's extreme), then the four row results are read as scalars.  No LDS
+// traffic, unlike shuffles through the LDS crossbar.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v, float id) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(id), __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float row_lanes(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
+  const float id = __builtin_huge_valf();
+  v = fminf(v, dpp_f<0xB1>(v, id));    // quad_perm [1,0,3,2]
+  v = fminf(v, dpp_f<0x4E>(v, id));    // quad_perm [2,3,0,1]
+  v = fminf(v, dpp_f<0x141>(v, id));   // row_half_mirror
+  v = fminf(v, dpp_f<0x140>(v, id));   // row_mirror
+  return fminf(fminf(row_lanes(v, 0), row_lanes(v, 16)), fminf(row_lanes(v, 32), row_lanes(v, 48)));
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
+  const float id = -__builtin_huge_valf();
+  v = fmaxf(v, dpp_f<0xB1>(v, id));
+  v = fmaxf(v, dpp_f<0x4E>(v, id));
+  v = fmaxf(v, dpp_f<0x141>(v, id));
+  v = fmaxf(v, dpp_f<0x140>(v, id));
+  return fmaxf(fmaxf(row_lanes(v, 0), row_lanes(v, 16)), fmaxf(row_lanes(v, 32), row_lanes(v, 48)));
+}
+// Value of lane l (wave-uniform l) as a scalar.
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, uint32_t l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
 }
 
 // Non-negative floats order like their bit patterns: atomics on the bits.

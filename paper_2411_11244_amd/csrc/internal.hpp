@@ -62,7 +62,7 @@ constexpr uint32_t kTraceRounds = 48;
 // A traversal workgroup appends at most its even share of a round's work items
 // plus kSegSlack (its waves' last, partial task group); segments are sized
 // from this so that the front and leaf-pair buffers cannot overflow.
-constexpr uint32_t kSegSlack = 8192;
+constexpr uint32_t kSegSlack = 16384;
 constexpr uint64_t kStackLimit = 1ull << 31;   // spill-stack entries (32 GiB)
 // Front entries expanded per round for segments of `seg` entries and nb
 // workgroups (each entry has at most 4 children when the round is large).

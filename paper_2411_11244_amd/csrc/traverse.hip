@@ -45,7 +45,7 @@ constexpr int kWavesPerBlock = kTravThreads / kWave;
 constexpr int kTravBlock = 768;                   // k_traverse: one 12-wave workgroup per CU
 constexpr int kTravWaves = kTravBlock / kWave;
 constexpr uint32_t kQueue = 320;  // per-wave LDS queue of triangle pairs (63 + 4 x 64)
-constexpr int kRows = 4;          // expansion rows per wave iteration
+constexpr int kRows = 12;         // expansion rows per wave iteration
 static_assert(kTravWaves * kRows * 64 + 256 <= (int)kSegSlack, "segment slack below one task group per wave");
 
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
@@ -99,8 +99,8 @@ __device__ __forceinline__ void improve_bound(uint32_t* target_base, size_t stri
   uint64_t am = __ballot(act);
   if (am == 0) return;
   uint32_t fl = first_lane(am);
-  uint32_t s0 = __shfl(slot, fl, 64);
-  uint32_t m0 = __shfl(mode, fl, 64);
+  uint32_t s0 = lane_value(slot, fl);
+  uint32_t m0 = lane_value(mode, fl);
   if (__ballot(act && slot != s0) == 0ull) {
     float r = act ? v : (m0 == 0 ? __builtin_huge_valf() : 0.f);
     r = m0 == 0 ? wave_min(r) : wave_max(r);
@@ -131,7 +131,7 @@ __device__ __forceinline__ void append(bool take, const E& e, E* buf, uint32_t* 
     base = atomicAdd(counter, cnt);
     if (base + cnt > cap) atomicOr(overflow, ovf_bit);
   }
-  base = __shfl(base, 0, 64);
+  base = lane_value(base, 0);
   if (take) {
     uint32_t idx = base + (uint32_t)__popcll(m & lt);
     if (idx < cap) buf[idx] = e;
@@ -276,14 +276,14 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
       best = fminf(best, wave_min(imp) + delta);
       float ext = wave_min(sel);
       uint32_t L = first_lane(__ballot(act && sel == ext));
-      a = __shfl(ca, L, 64);
-      b = __shfl(cb, L, 64);
+      a = lane_value(ca, L);
+      b = lane_value(cb, L);
     } else {
       best = fmaxf(best, fmaxf(wave_max(imp) - delta, 0.f));
       float ext = wave_max(sel);
       uint32_t L = first_lane(__ballot(act && sel == ext));
-      a = __shfl(ca, L, 64);
-      b = __shfl(cb, L, 64);
+      a = lane_value(ca, L);
+      b = lane_value(cb, L);
     }
   }
   {
@@ -499,7 +499,7 @@ __device__ __forceinline__ void append_rows(const bool* take, const uint4* e, ui
     base = atomicAdd(lds_count, tot);
     if (base + tot > seg) atomicOr(overflow, ovf_bit);
   }
-  base = __shfl(base, 0, 64);
+  base = lane_value(base, 0);
   uint4* out = buf + (uint64_t)blockIdx.x * seg;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -721,6 +721,10 @@ __device__ __forceinline__ void world_tri(const float* tris, uint32_t pos, const
   }
 }
 
+// LDS_SLOTS: the per-query running bound and window live in LDS (n_slots <=
+// kLdsSlots); a compile-time choice, so no load has to pick between LDS and
+// global memory at run time.
+template <bool LDS_SLOTS>
 __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   __shared__ BlockState bs_;
   __shared__ uint4 sq[kTravWaves][kQueue];
@@ -733,7 +737,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   const uint32_t gw = blockIdx.x * kTravWaves + wib;
   const uint32_t nw = gridDim.x * kTravWaves;
   uint4* q = sq[wib];
-  const bool lds_slots = p.n_slots <= kLdsSlots;
+  constexpr bool lds_slots = LDS_SLOTS;
   WaveStats ws;
 #pragma unroll
   for (int i = 0; i < ST_N; ++i) ws.v[i] = 0u;
@@ -1014,8 +1018,12 @@ hipError_t launch_slot_hist(const TravParams& p, uint32_t* live, hipStream_t s) 
 
 hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, uint32_t* threads) {
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_traverse, kTravBlock, 0);
+  int per_cu2 = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_traverse<true>, kTravBlock, 0);
   if (e != hipSuccess) return e;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k_traverse<false>, kTravBlock, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu2 < per_cu) per_cu = per_cu2;
   hipDeviceProp_t prop;
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) return e;
@@ -1032,7 +1040,8 @@ hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, u
 hipError_t launch_traverse(const TravParams& p, uint32_t blocks, uint32_t threads, hipStream_t s) {
   TravParams pp = p;
   void* args[] = {&pp};
-  return hipLaunchCooperativeKernel((const void*)k_traverse, dim3(blocks), dim3(threads), args, 0, s);
+  const void* fn = p.n_slots <= kLdsSlots ? (const void*)k_traverse<true> : (const void*)k_traverse<false>;
+  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(threads), args, 0, s);
 }
 
 hipError_t launch_reeval(const TravParams& p, hipStream_t s) {
