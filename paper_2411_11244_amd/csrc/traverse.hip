@@ -42,10 +42,10 @@ namespace gd {
 
 constexpr int kTravThreads = 256;                 // helper kernels
 constexpr int kWavesPerBlock = kTravThreads / kWave;
-constexpr int kTravBlock = 768;                   // k_traverse: one 12-wave workgroup per CU
+constexpr int kTravBlock = 1024;                  // k_traverse: one 16-wave workgroup per CU
 constexpr int kTravWaves = kTravBlock / kWave;
 constexpr uint32_t kQueue = 320;  // per-wave LDS queue of triangle pairs (63 + 4 x 64)
-constexpr int kRows = 12;         // expansion rows per wave iteration
+constexpr int kRows = 8;          // expansion rows per wave iteration
 static_assert(kTravWaves * kRows * 64 + 256 <= (int)kSegSlack, "segment slack below one task group per wave");
 
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
