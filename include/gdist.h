@@ -217,14 +217,15 @@ typedef struct {
   uint64_t front_capacity;  /* entries per front and per leaf-pair buffer (0 = 2^25, at
                                most 2^28); a step's rounds expand at most about a
                                quarter of it, the surplus waits on the spill stack       */
-  uint32_t cand_per_slot;   /* FP64 candidates per query (0 = 2^17, at most 2^26); a
-                               query that needs more fails with GDIST_E_CAPACITY        */
+  uint32_t cand_per_slot;   /* FP64 candidates per query (0 = 2^18, at most 2^26); a
+                               query that needs more is re-run alone (see fallbacks)    */
   uint32_t max_tris;        /* largest mesh a query refits, i.e. the smaller mesh of
                                its pair (0 = largest mesh built on the context when the
                                server starts); sizes the per-slot box storage            */
   uint32_t reserved;
   uint64_t stack_capacity;  /* spill-stack entries (0 = 2^26, at most 2^31); doubles when
-                               one query overflows it alone                              */
+                               one query overflows it alone; beyond 2^31 the query is
+                               re-run alone (see fallbacks)                              */
 } gdist_server_config_t;
 
 typedef struct {
@@ -239,7 +240,7 @@ typedef struct {
   uint64_t steps, rounds;
   uint32_t active, pending; /* at the time of the call                                    */
   uint32_t concurrency;     /* current admission limit (halved after a storage overflow) */
-  uint32_t reserved;
+  uint32_t fallbacks;       /* queries re-run alone through gdist_query's growing storage */
   double device_ms;         /* device time of all steps (HIP events)                     */
 } gdist_server_stats_t;
 

@@ -16,9 +16,10 @@
 // A spill-stack overflow puts every query in flight back at the head of the
 // queue (keeping its submit time), clears the traversal storage and halves the
 // concurrency limit; when a query overflows alone the stack doubles (up to
-// 2^31 entries) before it runs again, and beyond that it fails with
-// E_CAPACITY.  A query whose candidate region fills up fails with
-// E_CAPACITY once its traversal drains; the other queries are not affected.
+// 2^31 entries) before it runs again.  A query whose candidate region fills
+// up (or that overflows the largest stack alone) is re-run by itself through
+// the batched query path, whose storage grows as far as device memory allows;
+// the other queries are not affected.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -63,6 +64,7 @@ struct gdist_server {
   hipEvent_t ev[2] = {nullptr, nullptr};
   // slot table (worker thread only)
   std::vector<uint8_t> active;
+  uint32_t fallbacks = 0;
   std::vector<Pending> slot_req;
   std::vector<uint32_t> free_slots;
   uint32_t n_active = 0, round0 = 0, concurrency = 0, clean_steps = 0;
@@ -139,6 +141,24 @@ void complete(gdist_server* sv, uint64_t tag, uint64_t t_submit, const gdist_res
   sv->done.push_back(cpl);
   sv->stats.completed++;
   if (r.status != GDIST_OK) sv->stats.failed++;
+}
+
+// Re-run one query alone through the batched path (the server's stream is
+// idle: the worker calls this between steps).
+void run_alone(gdist_server* sv, const Pending& rq) {
+  gdist_result_t r;
+  std::memset(&r, 0, sizeof(r));
+  gdist_status_t s = run_queries(sv->c, 1, &rq.q, &r);
+  if (s != GDIST_OK) {
+    std::memset(&r, 0, sizeof(r));
+    r.status = (uint32_t)s;
+    r.distance = __builtin_nan("");
+  }
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    sv->fallbacks++;
+  }
+  complete(sv, rq.tag, rq.t_submit, r);
 }
 
 gdist_result_t failed_result(gdist_status_t s) {
@@ -257,8 +277,7 @@ gdist_status_t step(gdist_server* sv) {
       else if (g != GDIST_E_CAPACITY) return g;
     }
     if (!requeue) {
-      const Pending& rq = sv->slot_req[act[0]];
-      complete(sv, rq.tag, rq.t_submit, failed_result(GDIST_E_CAPACITY));
+      run_alone(sv, sv->slot_req[act[0]]);
     } else {
       std::lock_guard<std::mutex> g(sv->mu);
       for (auto it = act.rbegin(); it != act.rend(); ++it) sv->pending.push_front(sv->slot_req[*it]);
@@ -299,10 +318,7 @@ gdist_status_t step(gdist_server* sv) {
     sv->concurrency++;
     sv->clean_steps = 0;
   }
-  for (uint32_t s : bad) {
-    const Pending& rq = sv->slot_req[s];
-    complete(sv, rq.tag, rq.t_submit, failed_result(GDIST_E_CAPACITY));
-  }
+  for (uint32_t s : bad) run_alone(sv, sv->slot_req[s]);
   if (!fin.empty()) {
     char* stage = (char*)sv->pinned;
     const size_t list_off = sizeof(SlotDesc) * sv->S;
@@ -388,7 +404,7 @@ gdist_status_t gdist_server_start(gdist_ctx_t c, const gdist_server_config_t* co
   if (cf.rounds_per_step == 0) cf.rounds_per_step = 4;
   if (cf.front_capacity == 0) cf.front_capacity = 1ull << 25;
   if (cf.stack_capacity == 0) cf.stack_capacity = 1ull << 26;
-  if (cf.cand_per_slot == 0) cf.cand_per_slot = 1u << 17;
+  if (cf.cand_per_slot == 0) cf.cand_per_slot = 1u << 18;
   if (cf.max_tris == 0)
     for (auto& kv : c->meshes) cf.max_tris = std::max(cf.max_tris, kv.second->n_tris);
   if (cf.max_slots > 512 || cf.max_tris == 0 || cf.front_capacity > kServerCapLimit ||
@@ -491,6 +507,7 @@ gdist_status_t gdist_server_stats(gdist_server_t sv, gdist_server_stats_t* out) 
   out->active = sv->n_active;
   out->pending = (uint32_t)sv->pending.size();
   out->concurrency = sv->concurrency;
+  out->fallbacks = sv->fallbacks;
   return GDIST_OK;
 }
 

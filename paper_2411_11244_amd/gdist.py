@@ -84,11 +84,11 @@ class gdist_completion_t(C.Structure):
 class gdist_server_stats_t(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("submitted", "admitted", "completed", "failed", "requeued",
                                           "steps", "rounds")] + \
-               [(n, C.c_uint32) for n in ("active", "pending", "concurrency", "reserved")] + \
+               [(n, C.c_uint32) for n in ("active", "pending", "concurrency", "fallbacks")] + \
                [("device_ms", C.c_double)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _lib = None
