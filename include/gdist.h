@@ -157,6 +157,14 @@ gdist_status_t gdist_destroy(gdist_ctx_t ctx);
  */
 gdist_status_t gdist_set_option(gdist_ctx_t ctx, const char* key, double value);
 
+/* Route the context's device allocations through the caller (for example a
+ * framework's caching allocator): alloc(bytes, user) returns device memory or
+ * NULL (then the call that needed it returns E_OOM), free_(ptr, user) releases
+ * it.  Both NULL restores hipMalloc / hipFree.  Only on a context that holds
+ * no device memory yet (right after gdist_create), else E_INVALID. */
+gdist_status_t gdist_set_allocator(gdist_ctx_t ctx, void* (*alloc)(size_t, void*), void (*free_)(void*, void*),
+                                   void* user);
+
 /* ------------------------------------------------------------------ meshes */
 
 /* Build the f12 tree of a mesh on the device (Morton keys, radix sort, leaf
@@ -192,10 +200,27 @@ gdist_status_t gdist_query(gdist_ctx_t ctx, gdist_mesh_t a, gdist_mesh_t b,
 
 /* n queries in one persistent launch (one refit launch set, one traversal
  * launch, one re-evaluation).  Each query's result equals what gdist_query
- * returns for it alone.  out[i].status carries the per-query status; the call
- * returns the first non-OK status, or OK.  Synchronous. */
+ * returns for it alone.  out[i].status carries the per-query status (a query
+ * that could not complete, e.g. after E_CAPACITY, holds that status and a NaN
+ * distance); the call returns the first non-OK status, or OK.  Synchronous. */
 gdist_status_t gdist_query_batch(gdist_ctx_t ctx, uint32_t n, const gdist_query_desc_t* q,
                                  gdist_result_t* out);
+
+/* gdist_query_batch without waiting: the queries are validated (E_HANDLE /
+ * E_INVALID now) and copied, then run in submission order by a worker thread
+ * of the context after everything already queued on hip_stream (a hipStream_t,
+ * or NULL for no ordering).  out must stay valid until gdist_sync returns;
+ * it is written when the batch completes.  Any other call on the context
+ * (except gdist_mesh_info and further async submissions) first waits for the
+ * queued batches.  E_BUSY while a server runs on the context. */
+gdist_status_t gdist_query_batch_async(gdist_ctx_t ctx, uint32_t n, const gdist_query_desc_t* q,
+                                       gdist_result_t* out, void* hip_stream);
+
+/* Wait for every batch queued with gdist_query_batch_async; then, if
+ * hip_stream is not NULL, make later work on that stream wait for the
+ * context's device work too.  Returns the first failure among the completed
+ * batches since the previous gdist_sync (with its message), or OK. */
+gdist_status_t gdist_sync(gdist_ctx_t ctx, void* hip_stream);
 
 /* Counters of the most recent query call on this context. */
 gdist_status_t gdist_last_stats(gdist_ctx_t ctx, gdist_stats_t* out);

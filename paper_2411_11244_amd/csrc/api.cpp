@@ -36,11 +36,16 @@ gdist_status_t dalloc(gdist_ctx* c, size_t bytes, void** p) {
   if (c->memory_budget && c->bytes_held + bytes > c->memory_budget)
     return fail(GDIST_E_OOM, "device memory budget exceeded (%llu + %zu > %llu bytes)",
                 (unsigned long long)c->bytes_held, bytes, (unsigned long long)c->memory_budget);
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return fail(GDIST_E_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  if (c->alloc_fn) {
+    *p = c->alloc_fn(bytes, c->alloc_user);
+    if (!*p) return fail(GDIST_E_OOM, "the caller's allocator returned NULL for %zu bytes", bytes);
+  } else {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return fail(GDIST_E_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
   }
   c->bytes_held += bytes;
   return GDIST_OK;
@@ -48,8 +53,52 @@ gdist_status_t dalloc(gdist_ctx* c, size_t bytes, void** p) {
 
 void dfree(gdist_ctx* c, void* p, size_t bytes) {
   if (!p) return;
-  (void)hipFree(p);
+  if (c->free_fn) c->free_fn(p, c->alloc_user);
+  else (void)hipFree(p);
   c->bytes_held -= bytes ? bytes : 256;
+}
+
+// Wait until every asynchronous batch of the context has finished (other
+// calls on the context do this first, so they never race with the worker).
+void drain_async(gdist_ctx* c) {
+  std::unique_lock<std::mutex> lk(c->amu);
+  c->acv.wait(lk, [&] { return c->apending == 0; });
+}
+
+void async_worker(gdist_ctx* c) {
+  (void)hipSetDevice(c->device);
+  for (;;) {
+    gdist_ctx::AsyncBatch b;
+    {
+      std::unique_lock<std::mutex> lk(c->amu);
+      c->acv.wait(lk, [&] { return c->astop || !c->aq.empty(); });
+      if (c->aq.empty()) return;   // stopping, nothing left
+      b = std::move(c->aq.front());
+      c->aq.pop_front();
+    }
+    gdist_status_t s = GDIST_OK;
+    if (b.after && hipStreamWaitEvent(c->stream, b.after, 0) != hipSuccess)
+      s = fail(GDIST_E_DEVICE, "hipStreamWaitEvent on the caller's stream failed");
+    if (s == GDIST_OK) s = run_queries(c, (uint32_t)b.q.size(), b.q.data(), b.out);
+    if (b.after) (void)hipEventDestroy(b.after);
+
+    std::lock_guard<std::mutex> g(c->amu);
+    if (s != GDIST_OK && c->aerr_status == GDIST_OK) {
+      c->aerr_status = s;
+      c->aerr_msg = t_err;
+    }
+    c->apending--;
+    c->acv.notify_all();
+  }
+}
+
+void stop_async(gdist_ctx* c) {
+  {
+    std::lock_guard<std::mutex> g(c->amu);
+    c->astop = true;
+  }
+  c->acv.notify_all();
+  if (c->aworker.joinable()) c->aworker.join();
 }
 
 gdist_status_t ensure(gdist_ctx* c, DevBuf& b, size_t bytes) {
@@ -396,7 +445,15 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
       c->group_hint = group;
       continue;
     }
-    if (s != GDIST_OK) return s;
+    if (s != GDIST_OK) {
+      // the queries from this group on did not complete: their results carry the failure
+      for (uint32_t i = g0; i < n; ++i) {
+        std::memset(&out[i], 0, sizeof(gdist_result_t));
+        out[i].status = (uint32_t)s;
+        out[i].distance = __builtin_nan("");
+      }
+      return s;
+    }
     g0 += gn;
   }
   float ms = 0.f;
@@ -460,6 +517,8 @@ gdist_status_t gdist_create(int device, gdist_ctx_t* out) {
 gdist_status_t gdist_destroy(gdist_ctx_t c) {
   if (!c) return GDIST_OK;
   if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  drain_async(c);
+  stop_async(c);
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto& kv : c->meshes) {
@@ -484,6 +543,7 @@ gdist_status_t gdist_destroy(gdist_ctx_t c) {
 gdist_status_t gdist_set_option(gdist_ctx_t c, const char* key, double v) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
   if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  drain_async(c);
   if (!key) return fail(GDIST_E_INVALID, "NULL key");
   auto u32opt = [&](uint32_t* dst, double lo, double hi) -> gdist_status_t {
     if (!(v >= lo && v <= hi) || v != std::floor(v))
@@ -529,6 +589,7 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
                            uint32_t flags, gdist_mesh_t* out) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
   if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  drain_async(c);
   if (!out) return fail(GDIST_E_INVALID, "NULL output handle pointer");
   *out = 0;
   if (!verts || !tris) return fail(GDIST_E_INVALID, "NULL vertex or triangle array");
@@ -632,6 +693,7 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
 gdist_status_t gdist_release(gdist_ctx_t c, gdist_mesh_t h) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
   if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  drain_async(c);
   Mesh* m = find_mesh(c, h);
   if (!m) return fail(GDIST_E_HANDLE, "unknown mesh handle %llu", (unsigned long long)h);
   HIPCHK(hipSetDevice(c->device));
@@ -660,6 +722,7 @@ gdist_status_t gdist_mesh_info(gdist_ctx_t c, gdist_mesh_t h, gdist_mesh_info_t*
 
 gdist_status_t gdist_mesh_export(gdist_ctx_t c, gdist_mesh_t h, float* boxes, float* tris, uint32_t* orig) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  drain_async(c);
   Mesh* m = find_mesh(c, h);
   if (!m) return fail(GDIST_E_HANDLE, "unknown mesh handle %llu", (unsigned long long)h);
   HIPCHK(hipSetDevice(c->device));
@@ -673,6 +736,7 @@ gdist_status_t gdist_query(gdist_ctx_t c, gdist_mesh_t a, gdist_mesh_t b, const 
                            const gdist_pose_t* pb, gdist_mode_t mode, gdist_result_t* out) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
   if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  drain_async(c);
   if (!out) return fail(GDIST_E_INVALID, "NULL result pointer");
   if (!pa || !pb) return fail(GDIST_E_INVALID, "NULL pose");
   gdist_query_desc_t d;
@@ -689,12 +753,92 @@ gdist_status_t gdist_query(gdist_ctx_t c, gdist_mesh_t a, gdist_mesh_t b, const 
 gdist_status_t gdist_query_batch(gdist_ctx_t c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
   if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  drain_async(c);
   HIPCHK(hipSetDevice(c->device));
   return run_queries(c, n, q, out);
 }
 
+gdist_status_t gdist_query_batch_async(gdist_ctx_t c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out,
+                                       void* hip_stream) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  if (n == 0) return GDIST_OK;
+  if (!q || !out) return fail(GDIST_E_INVALID, "NULL query or result array");
+  for (uint32_t i = 0; i < n; ++i) {   // validate now: errors surface at submit
+    SlotDesc d;
+    Mesh* B = nullptr;
+    gdist_status_t s = make_slot(c, q[i], i, &d, &B);
+    if (s != GDIST_OK) return s;
+  }
+  HIPCHK(hipSetDevice(c->device));
+  gdist_ctx::AsyncBatch b;
+  b.q.assign(q, q + n);
+  b.out = out;
+  if (hip_stream) {
+    HIPCHK(hipEventCreateWithFlags(&b.after, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(b.after, (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(b.after);
+      return fail(GDIST_E_DEVICE, "hipEventRecord on the caller's stream failed: %s", hipGetErrorString(e));
+    }
+  }
+  {
+    std::lock_guard<std::mutex> g(c->amu);
+    if (!c->aworker.joinable()) {
+      c->astop = false;
+      c->aworker = std::thread(async_worker, c);
+    }
+    c->aq.push_back(std::move(b));
+    c->apending++;
+  }
+  c->acv.notify_all();
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_sync(gdist_ctx_t c, void* hip_stream) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  drain_async(c);
+  gdist_status_t s;
+  std::string msg;
+  {
+    std::lock_guard<std::mutex> g(c->amu);
+    s = c->aerr_status;
+    msg = c->aerr_msg;
+    c->aerr_status = GDIST_OK;
+    c->aerr_msg.clear();
+  }
+  if (hip_stream) {
+    // later work on the caller's stream starts after everything queued so far
+    hipEvent_t ev = nullptr;
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, c->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)hip_stream, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return fail(GDIST_E_DEVICE, "ordering the caller's stream failed: %s", hipGetErrorString(e));
+  }
+  if (s != GDIST_OK) return fail(s, "%s", msg.c_str());
+  return GDIST_OK;
+}
+
+gdist_status_t gdist_set_allocator(gdist_ctx_t c, void* (*alloc)(size_t, void*), void (*free_)(void*, void*),
+                                   void* user) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  drain_async(c);
+  if ((alloc == nullptr) != (free_ == nullptr)) return fail(GDIST_E_INVALID, "give both allocator functions or neither");
+  if (c->bytes_held != 0)
+    return fail(GDIST_E_INVALID, "the context already holds %llu device bytes; set the allocator right after "
+                "gdist_create", (unsigned long long)c->bytes_held);
+  c->alloc_fn = alloc;
+  c->free_fn = free_;
+  c->alloc_user = user;
+  return GDIST_OK;
+}
+
 gdist_status_t gdist_last_stats(gdist_ctx_t c, gdist_stats_t* out) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  drain_async(c);
   if (!out) return fail(GDIST_E_INVALID, "NULL output");
   *out = c->last;
   return GDIST_OK;
@@ -703,6 +847,7 @@ gdist_status_t gdist_last_stats(gdist_ctx_t c, gdist_stats_t* out) {
 gdist_status_t gdist_eval_box_bounds(gdist_ctx_t c, uint32_t n, const float* a, const float* b, float* out) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
   if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  drain_async(c);
   if (n == 0) return GDIST_OK;
   if (!a || !b || !out) return fail(GDIST_E_INVALID, "NULL array");
   HIPCHK(hipSetDevice(c->device));
@@ -727,6 +872,7 @@ gdist_status_t gdist_eval_tri_tri(gdist_ctx_t c, uint32_t n, const float* p, con
                                   float* out32, double* out64) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
   if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  drain_async(c);
   if (n == 0) return GDIST_OK;
   if (!p || !q || !out32 || !out64) return fail(GDIST_E_INVALID, "NULL array");
   if (mode > 1) return fail(GDIST_E_INVALID, "unknown mode %u", mode);

@@ -1,9 +1,14 @@
 // Host-side definitions shared by the C ABI (api.cpp) and the serving core
 // (server.cpp): contexts, mesh handles, device buffers and helpers.
 #pragma once
+#include <condition_variable>
 #include <cstdarg>
+#include <deque>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <unordered_map>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -46,6 +51,7 @@ gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx
 // The batched query path (refit, grouped traversal with growing storage,
 // FP64 re-evaluation) on the context's stream and workspace.
 gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out);
+void drain_async(gdist_ctx* c);
 
 }  // namespace gd
 
@@ -75,5 +81,23 @@ struct gdist_ctx {
   unsigned long long last_ctl_sum[gd::ST_N] = {};
   gdist_stats_t last{};
   bool busy = false;                       // a server owns the stream and workspace
+  // caller-supplied device allocator (gdist_set_allocator); hipMalloc when unset
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*free_fn)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
+  // asynchronous batches (gdist_query_batch_async), run in order by a worker thread
+  struct AsyncBatch {
+    std::vector<gdist_query_desc_t> q;
+    gdist_result_t* out = nullptr;
+    hipEvent_t after = nullptr;            // the caller's stream position to wait for
+  };
+  std::mutex amu;
+  std::condition_variable acv;
+  std::deque<AsyncBatch> aq;
+  std::thread aworker;
+  bool astop = false;
+  uint32_t apending = 0;                   // queued or running batches
+  gdist_status_t aerr_status = GDIST_OK;   // first failure since the last gdist_sync
+  std::string aerr_msg;
 };
 

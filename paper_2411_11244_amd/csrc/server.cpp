@@ -394,6 +394,7 @@ gdist_status_t gdist_server_start(gdist_ctx_t c, const gdist_server_config_t* co
   if (!out) return fail(GDIST_E_INVALID, "NULL output pointer");
   *out = nullptr;
   if (c->busy) return fail(GDIST_E_BUSY, "the context already runs a server");
+  drain_async(c);
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(hipStreamSynchronize(c->stream));
   gdist_server* sv = new gdist_server();

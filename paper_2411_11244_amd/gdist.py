@@ -91,6 +91,9 @@ class gdist_server_stats_t(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
 _lib = None
 
 
@@ -102,6 +105,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2411_11244_amd/build_lib.py "
                            "(or __graft_entry__.build()); there is no fallback path")
+    # PyTorch ships its own HIP runtime under the same soname.  Loading torch
+    # first makes this library bind to that one runtime; loading it second
+    # would put two HIP runtimes in the process, and the later one finds no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     st, vp, u32, u64, fp, dp = C.c_int, C.c_void_p, C.c_uint32, C.c_uint64, C.c_void_p, C.c_void_p
     sig = {
@@ -118,6 +128,9 @@ def lib():
         "gdist_last_stats": [vp, C.POINTER(gdist_stats_t)],
         "gdist_eval_box_bounds": [vp, u32, fp, fp, fp],
         "gdist_eval_tri_tri": [vp, u32, fp, fp, u32, fp, dp],
+        "gdist_query_batch_async": [vp, u32, C.POINTER(gdist_query_desc_t), C.POINTER(gdist_result_t), vp],
+        "gdist_sync": [vp, vp],
+        "gdist_set_allocator": [vp, ALLOC_FN, FREE_FN, vp],
         "gdist_server_start": [vp, C.POINTER(gdist_server_config_t), C.POINTER(vp)],
         "gdist_server_submit": [vp, C.POINTER(gdist_query_desc_t), u64],
         "gdist_server_stats": [vp, C.POINTER(gdist_server_stats_t)],
@@ -140,7 +153,7 @@ def exported_symbols() -> List[str]:
             "gdist_mesh_info", "gdist_mesh_export", "gdist_query", "gdist_query_batch",
             "gdist_last_stats", "gdist_last_error", "gdist_eval_box_bounds", "gdist_eval_tri_tri",
             "gdist_server_start", "gdist_server_submit", "gdist_server_poll", "gdist_server_stats",
-            "gdist_server_stop"]
+            "gdist_server_stop", "gdist_query_batch_async", "gdist_sync", "gdist_set_allocator"]
 
 
 def gdist_last_error() -> str:
@@ -180,7 +193,8 @@ def gdist_create(device: int = 0) -> int:
 
 
 def gdist_destroy(ctx: int) -> None:
-    _check(lib().gdist_destroy(ctx))
+    _check(lib().gdist_destroy(ctx))   # waits for queued asynchronous batches first
+    _in_flight.pop(ctx, None)
 
 
 def gdist_set_option(ctx: int, key: str, value: float) -> None:
@@ -258,6 +272,52 @@ def gdist_query_batch(ctx: int, descs: Sequence[gdist_query_desc_t], check: bool
     if check:
         _check(st)
     return [res[i].as_dict() for i in range(n)]
+
+
+class AsyncBatch:
+    """Results of a gdist_query_batch_async call; read them after gdist_sync."""
+
+    def __init__(self, descs):
+        self.n = len(descs)
+        self.descs = (gdist_query_desc_t * self.n)(*descs)
+        self.res = (gdist_result_t * self.n)()
+
+    def results(self) -> List[dict]:
+        return [self.res[i].as_dict() for i in range(self.n)]
+
+
+# Batches in flight per context: the library writes their result arrays after
+# the submitting call returns, so they stay referenced until gdist_sync.
+_in_flight: dict = {}
+
+
+def gdist_query_batch_async(ctx: int, descs: Sequence[gdist_query_desc_t], stream=None) -> AsyncBatch:
+    """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
+    b = AsyncBatch(descs)
+    h = getattr(stream, "cuda_stream", stream)
+    _check(lib().gdist_query_batch_async(ctx, b.n, b.descs, b.res, h))
+    _in_flight.setdefault(ctx, []).append(b)
+    return b
+
+
+def gdist_sync(ctx: int, stream=None) -> None:
+    h = getattr(stream, "cuda_stream", stream)
+    try:
+        _check(lib().gdist_sync(ctx, h))
+    finally:
+        _in_flight.pop(ctx, None)
+
+
+def gdist_set_allocator(ctx: int, alloc=None, free=None, user=None) -> tuple:
+    """alloc(nbytes, user) -> device pointer (int), free(ptr, user) -> None; both
+    None restores hipMalloc.  Returns the ctypes callbacks, which the caller must
+    keep alive for as long as the context uses them."""
+    if alloc is None and free is None:
+        _check(lib().gdist_set_allocator(ctx, ALLOC_FN(), FREE_FN(), user))
+        return ()
+    a, f = ALLOC_FN(alloc), FREE_FN(free)
+    _check(lib().gdist_set_allocator(ctx, a, f, user))
+    return (a, f)
 
 
 def gdist_last_stats(ctx: int) -> dict:

@@ -1,0 +1,122 @@
+"""Asynchronous batches (gdist_query_batch_async / gdist_sync) and a caller-
+supplied device allocator (gdist_set_allocator), through the C ABI.
+
+An asynchronous batch must return exactly what the synchronous call returns
+for the same queries; a context routed through the caller's allocator must
+return exactly what a default context returns.
+"""
+import numpy as np
+import pytest
+
+import meshgen as g
+from paper_2411_11244_amd import gdist
+
+pytestmark = pytest.mark.gpu
+
+
+def _same(r, a):
+    assert r["status"] == a["status"] == 0
+    assert r["distance"] == a["distance"]
+    assert (r["tri_a"], r["tri_b"]) == (a["tri_a"], a["tri_b"])
+    assert r["n_ties"] == a["n_ties"]
+    assert np.array_equal(r["point_a"], a["point_a"]) and np.array_equal(r["point_b"], a["point_b"])
+
+
+def _workload(ctx, seed, n):
+    rng = np.random.default_rng(seed)
+    pool = [g.torus(40, 20, 1.0, 0.3), g.icosphere(8, 1.0, 1e-3, rng), g.random_soup(rng, 1500, 1.0, 0.1),
+            g.heightfield(30, 0.02, rng)]
+    hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in pool]
+    qs = g.serving_stream(pool, 1000.0, n, seed=seed + 1)
+    return hs, [gdist.make_desc(hs[q.a], hs[q.b], q.pose_a, q.pose_b, q.mode) for q in qs]
+
+
+def test_async_equals_sync(gctx):
+    import torch
+    hs, descs = _workload(gctx, 11, 40)
+    try:
+        want1 = gdist.gdist_query_batch(gctx, descs[:25])
+        want2 = gdist.gdist_query_batch(gctx, descs[25:])
+        s = torch.cuda.current_stream()
+        b1 = gdist.gdist_query_batch_async(gctx, descs[:25])
+        b2 = gdist.gdist_query_batch_async(gctx, descs[25:], stream=s)
+        gdist.gdist_sync(gctx, s)
+        for r, a in zip(b1.results() + b2.results(), want1 + want2):
+            _same(r, a)
+        # another call on the context waits for queued batches by itself
+        b3 = gdist.gdist_query_batch_async(gctx, descs[:10])
+        d = descs[10]
+        r = gdist.gdist_query(gctx, d.a, d.b, (np.array(d.pa.R).reshape(3, 3), np.array(d.pa.t)),
+                              (np.array(d.pb.R).reshape(3, 3), np.array(d.pb.t)), d.mode)
+        _same(r, want1[10])
+        for r, a in zip(b3.results(), want1[:10]):
+            _same(r, a)
+        gdist.gdist_sync(gctx)
+    finally:
+        for h in hs:
+            gdist.gdist_release(gctx, h)
+
+
+def test_async_errors(gctx):
+    m = g.torus(48, 24, 1.0, 0.3)
+    I = g.identity_pose()
+    h = gdist.gdist_build(gctx, m.verts, m.tris)
+    try:
+        with pytest.raises(gdist.GdistError) as e:
+            gdist.gdist_query_batch_async(gctx, [gdist.make_desc(h, h + 77, I, I, 0)])
+        assert e.value.status == gdist.GDIST_E_HANDLE
+        gdist.gdist_sync(gctx)   # nothing queued: OK
+    finally:
+        gdist.gdist_release(gctx, h)
+    # a batch that fails while running reports its status at gdist_sync
+    ctx = gdist.gdist_create(0)
+    try:
+        h = gdist.gdist_build(ctx, m.verts, m.tris)
+        for key, v in (("max_retries", 0), ("front_capacity", 64), ("stack_capacity", 64), ("expand_budget", 4)):
+            gdist.gdist_set_option(ctx, key, v)
+        pending = gdist.gdist_query_batch_async(ctx, [gdist.make_desc(h, h, I, I, 0)])
+        with pytest.raises(gdist.GdistError) as e:
+            gdist.gdist_sync(ctx)
+        assert pending.results()[0]["status"] == gdist.GDIST_E_CAPACITY
+        assert e.value.status == gdist.GDIST_E_CAPACITY
+        gdist.gdist_sync(ctx)    # the failure was reported once
+    finally:
+        gdist.gdist_destroy(ctx)
+
+
+def test_caller_allocator(gctx):
+    import torch
+    live, counts = {}, {"alloc": 0, "free": 0}
+
+    def alloc(n, user):
+        p = torch.cuda.caching_allocator_alloc(int(n))
+        live[p] = n
+        counts["alloc"] += 1
+        return p
+
+    def free(p, user):
+        live.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+        counts["free"] += 1
+
+    hs, descs = _workload(gctx, 21, 16)
+    try:
+        want = gdist.gdist_query_batch(gctx, descs)
+    finally:
+        for h in hs:
+            gdist.gdist_release(gctx, h)
+    ctx = gdist.gdist_create(0)
+    try:
+        keep = gdist.gdist_set_allocator(ctx, alloc, free)
+        hs2, descs2 = _workload(ctx, 21, 16)
+        got = gdist.gdist_query_batch(ctx, descs2)
+        for r, a in zip(got, want):
+            _same(r, a)
+        assert counts["alloc"] > 0 and live
+        with pytest.raises(gdist.GdistError) as e:
+            gdist.gdist_set_allocator(ctx)   # the context already holds memory
+        assert e.value.status == gdist.GDIST_E_INVALID
+    finally:
+        gdist.gdist_destroy(ctx)
+    assert not live and counts["free"] == counts["alloc"]
+    del keep
