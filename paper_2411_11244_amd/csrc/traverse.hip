@@ -602,15 +602,22 @@ __device__ __forceinline__ void spill_wave(const BlockState* bs, const Round& rd
 // pair's 1-2 triangles of each side once, gives each of the (up to 4)
 // triangle pairs the cheap separating-axis test, and pushes the survivors
 // onto the wave's LDS queue (at most 4 x 64 per call).
-__device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base,
-                                                   uint32_t n_items, uint32_t lane, uint64_t lt, uint4* q,
-                                                   uint32_t& qn, WaveStats& ws) {
+// The leaf-pair entries [base, base + 64) of the current round (lane order);
+// lanes past n_items get an inactive placeholder.
+__device__ __forceinline__ uint4 leaf_row(const BlockState* bs, const Round& rd, uint32_t base, uint32_t n_items,
+                                          uint32_t lane) {
   const uint32_t it = base + lane;
-  bool act = it < n_items;
   uint4 ent = make_uint4(1u, 1u, 0u, 0u);
   const uint32_t il = n_items - 1u < base + 63u ? n_items - 1u : base + 63u;
-  const uint32_t addr = row_addr(bs->lpre, rd.nb, rd.seg_l, base, il, act ? it : il, lane);
-  if (act) ent = rd.lin[addr];
+  const uint32_t addr = row_addr(bs->lpre, rd.nb, rd.seg_l, base, il, it < n_items ? it : il, lane);
+  if (it < n_items) ent = rd.lin[addr];
+  return ent;
+}
+
+__device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base,
+                                                   uint32_t n_items, uint4 ent, uint32_t lane, uint64_t lt, uint4* q,
+                                                   uint32_t& qn, WaveStats& ws) {
+  bool act = base + lane < n_items;
   const uint32_t slot = ent.w;
   const SlotView v = slot_view(p, bs, rd.lds_slots, act, slot);
   const uint32_t mode = v.mode;
@@ -805,11 +812,17 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     // expansion work is handed out in groups of kRows waves' worth of items
     const uint32_t total = spill_end + (uint32_t)(((uint64_t)exp_items + 64u * kRows - 1u) / (64u * kRows));
     uint32_t qn = 0;  // wave-uniform fill of this wave's LDS queue
+    // a leaf task's entries are loaded one task ahead, so their latency
+    // overlaps the previous task's triangle loads
+    uint4 lent = gw < leaf_waves ? leaf_row(bs, rd, gw * 64u, nl, lane) : make_uint4(1u, 1u, 0u, 0u);
     for (uint32_t w = gw;;) {
       const bool more = w < total;
       if (more) {
-        if (w < leaf_waves) narrow_filter_wave(p, bs, rd, w * 64u, nl, lane, lt, q, qn, ws);
-        else if (w < spill_end) spill_wave(bs, rd, (w - leaf_waves) * 64u, lane);
+        if (w < leaf_waves) {
+          const uint4 cur = lent;
+          if (w + nw < leaf_waves) lent = leaf_row(bs, rd, (w + nw) * 64u, nl, lane);
+          narrow_filter_wave(p, bs, rd, w * 64u, nl, cur, lane, lt, q, qn, ws);
+        } else if (w < spill_end) spill_wave(bs, rd, (w - leaf_waves) * 64u, lane);
         else expand_rows<kRows>(p, bs, rd, (w - spill_end) * 64u * kRows, exp_items, kk, lane, lt, ws);
         w += nw;
       }
