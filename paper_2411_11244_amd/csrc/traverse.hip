@@ -342,7 +342,6 @@ constexpr uint32_t kLdsSlots = 512;
 struct BlockState {
   uint32_t fpre[kMaxBlocks + 2];   // prefix of the current front's segment counts
   uint32_t lpre[kMaxBlocks + 2];   // (workgroup segments + admission segment)
-  uint32_t scan[kTravBlock];
   uint32_t fo, lo;                 // this workgroup's appends in the current round
   uint32_t best[kLdsSlots];        // per-slot running bound (float bits), refreshed each round
   float delta[kLdsSlots];
@@ -451,33 +450,31 @@ __device__ __forceinline__ SlotView slot_view(const TravParams& p, const BlockSt
   return v;
 }
 
-// Exclusive prefix over nb <= 4 * kTravBlock counts; pre[nb] = total.
-__device__ __forceinline__ void block_prefix(const uint32_t* cnt, uint32_t nb, uint32_t* pre, uint32_t* tmp) {
-  const uint32_t t = threadIdx.x;
-  uint32_t v[4], s = 0;
+// Exclusive prefix over nb <= 1024 counts, pre[nb] = total, computed by one
+// wave (lane l owns counts [16 l, 16 l + 16)): no workgroup barriers.
+__device__ __forceinline__ void wave_prefix(const uint32_t* __restrict__ cnt, uint32_t nb, uint32_t* pre,
+                                            uint32_t lane) {
+  uint32_t v[16], sum = 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    uint32_t idx = 4u * t + i;
+  for (int i = 0; i < 16; ++i) {
+    const uint32_t idx = 16u * lane + i;
     v[i] = idx < nb ? cnt[idx] : 0u;
-    s += v[i];
+    sum += v[i];
   }
-  tmp[t] = s;
-  __syncthreads();
-  for (uint32_t off = 1; off < kTravBlock; off <<= 1) {
-    uint32_t x = t >= off ? tmp[t - off] : 0u;
-    __syncthreads();
-    tmp[t] += x;
-    __syncthreads();
-  }
-  uint32_t run = tmp[t] - s;
+  uint32_t incl = sum;   // inclusive scan of the lane sums
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    uint32_t idx = 4u * t + i;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t up = __shfl_up(incl, o, 64);
+    if (lane >= (uint32_t)o) incl += up;
+  }
+  uint32_t run = incl - sum;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const uint32_t idx = 16u * lane + i;
     if (idx < nb) pre[idx] = run;
     run += v[i];
   }
-  if (t == kTravBlock - 1) pre[nb] = tmp[t];
-  __syncthreads();
+  if (lane == 63u) pre[nb] = incl;
 }
 
 // Append the lanes flagged in R rows to this workgroup's segment of `buf`
@@ -771,8 +768,10 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     rd.stk = p.stack;
     if (lds_slots)
       for (uint32_t s = tid; s < p.n_slots; s += kTravBlock) bs->best[s] = ld_rlx(&p.st[s].best);
-    block_prefix(p.fcount[round & 1u], rd.nb, bs->fpre, bs->scan);
-    block_prefix(p.lcount[round & 1u], rd.nb, bs->lpre, bs->scan);
+    // segment prefixes of this round's inputs: wave 0 the front, wave 1 the leaf pairs
+    if (wib == 0u) wave_prefix(p.fcount[round & 1u], rd.nb, bs->fpre, lane);
+    else if (wib == 1u) wave_prefix(p.lcount[round & 1u], rd.nb, bs->lpre, lane);
+    __syncthreads();
     const uint32_t n = bs->fpre[rd.nb];
     const uint32_t nl = bs->lpre[rd.nb];
     // Bounded memory: at most round_cap front entries are expanded per round.
