@@ -69,8 +69,14 @@ __device__ void grid_sync(Ctl* c, uint32_t spin_limit) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __builtin_amdgcn_s_waitcnt(0);
     uint32_t gen = ld_rlx(&c->bar_gen);
-    uint32_t arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    // relaxed arrival: the release fence above already orders this
+    // workgroup's writes before it (each cache writeback and invalidate is a
+    // round's fixed cost, so every workgroup does one of each)
+    uint32_t arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == gridDim.x - 1) {
+      // the last arrival acquires every workgroup's release, then publishes
+      // the next generation (after the count reset) with a release store
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       st_rlx(&c->bar_count, 0u);
       __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
