@@ -120,13 +120,17 @@ def main():
             "unit": "GB/s", "frac": round(trav_gbs / HBM_PEAK_GBS, 4),
             "traffic": pmc["traffic_bytes_per_launch"] if pmc else None,
             "traffic_gbs": round(pmc["traffic_bytes_per_launch"] / (avg_launch_ms * 1e-3) / 1e9, 1) if pmc else None,
+            "traffic_frac": round(pmc["traffic_bytes_per_launch"] / (avg_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                            if pmc else None,
             "traffic_note": ("HBM bytes per launch, rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a copy kernel "
                              "(profiles/k_traverse_rings_traffic.md)") if pmc else
                             "null: no PMC summary for the current kernel sources and launch options",
             "algorithmic_bytes_per_launch": int(trav_bytes / max(1, trav_launches)),
             "avg_ms_per_launch": round(avg_launch_ms, 5), "launches": int(trav_launches),
             "bytes_per_unit": "16 B per entry popped + 48 B per child pair + 16 B per entry pushed; "
-                              "16 B per leaf pair + 72 B per triangle pair + 16 B per candidate"}
+                              "16 B per leaf pair + 72 B per triangle pair + 16 B per candidate",
+            "note": "algorithmic bytes count every box and triangle gather; most hit in L1/L2, so "
+                    "achieved can exceed the HBM peak while traffic (real HBM bytes) stays below it"}
     N, L = info["n_tris"], info["n_leaves"]
     refit_bytes = 36 * N + 24 * (2 * L - 1)
     refit_ms = float(np.mean([s["ms_refit"] for s in stats])) / args.frames
