@@ -236,6 +236,14 @@ gdist_status_t gdist_last_stats(gdist_ctx_t ctx, gdist_stats_t* out);
  * server runs, other query calls on its context return GDIST_E_BUSY. */
 typedef struct gdist_server* gdist_server_t;
 
+/* A device step is a fixed launch sequence after admission: the traversal
+ * (at most rounds_per_step rounds), per-slot live counts, completion flags,
+ * FP64 re-evaluation of the completed slots, one copy of the step's report to
+ * pinned host memory.  By default the server captures it once as a HIP graph
+ * and replays it every step (one graph launch and one host wait per step);
+ * with this flag it launches the kernels one by one (same results). */
+#define GDIST_SERVER_DIRECT 1u
+
 typedef struct {
   uint32_t max_slots;       /* queries in flight, 1..512 (0 = 64)                        */
   uint32_t rounds_per_step; /* traversal rounds per device step (0 = 4)                  */
@@ -247,7 +255,7 @@ typedef struct {
   uint32_t max_tris;        /* largest mesh a query refits, i.e. the smaller mesh of
                                its pair (0 = largest mesh built on the context when the
                                server starts); sizes the per-slot box storage            */
-  uint32_t reserved;
+  uint32_t flags;           /* GDIST_SERVER_DIRECT, or 0                                 */
   uint64_t stack_capacity;  /* spill-stack entries (0 = 2^26, at most 2^31); doubles when
                                one query overflows it alone; beyond 2^31 the query is
                                re-run alone (see fallbacks)                              */
@@ -266,7 +274,11 @@ typedef struct {
   uint32_t active, pending; /* at the time of the call                                    */
   uint32_t concurrency;     /* current admission limit (halved after a storage overflow) */
   uint32_t fallbacks;       /* queries re-run alone through gdist_query's growing storage */
-  double device_ms;         /* device time of all steps (HIP events)                     */
+  double device_ms;         /* device time of all steps' launch sequences (HIP events)    */
+  uint64_t graph_steps;     /* steps replayed from the captured graph                     */
+  uint32_t graph_mode;      /* 0: kernels launched one by one; 1: stream-captured graph;
+                               2: graph with an explicit cooperative traversal node      */
+  uint32_t reserved;
 } gdist_server_stats_t;
 
 /* Start a server on ctx (config may be NULL for defaults).  Allocates all of

@@ -43,7 +43,7 @@ struct SlotState {
   uint32_t n_admitted;       // candidates that passed the final window
   uint32_t n_cand;           // candidates appended to this slot's region
   uint32_t cand_overflow;    // the region filled up
-  uint32_t pad;
+  uint32_t active;           // the slot's query is in flight (set at admission, cleared at completion)
 };
 
 // Candidate triangle pair for FP64 re-evaluation (positions in leaf order).
@@ -84,7 +84,8 @@ struct Ctl {
   uint32_t bar_gen;
   uint32_t rounds_done;    // rounds completed by the latest launch
   uint32_t stack_top[2];   // spill-stack height at the start of a round of parity i
-  uint32_t pad;
+  uint32_t round_base;     // rounds run by earlier stepped launches (serving); a launch's
+                           //   first round is round0 + round_base
   unsigned long long stats[ST_N];
   // per-round device timestamps (constant-rate wall clock) and front sizes
   unsigned long long trace_t[kTraceRounds];
@@ -119,6 +120,18 @@ struct TravParams {
   uint32_t max_rounds;     // rounds this launch may run (the serving step)
   uint32_t cand_stop;      // 1: a candidate-region overflow also stops the launch (the caller retries
                            //    with larger regions); 0: it only marks the slot
+  const uint32_t* finish;  // re-evaluation over slots 0 .. n_list-1 where finish[slot] == 1
+                           //   (nullptr: every listed slot)
+};
+
+// Head of the report of one serving step (device buffer, copied to pinned
+// host memory at the step's end); per-slot arrays follow at offsets the host
+// computes: live entries (u32), completion flags (u32), results.
+struct StepHead {
+  uint32_t overflow;       // the traversal's Ctl::overflow and Ctl::abort
+  uint32_t abort;
+  uint32_t rounds_done;
+  uint32_t pad;
 };
 
 // build.hip
@@ -164,6 +177,14 @@ hipError_t launch_reeval(const TravParams& p, hipStream_t s);
 hipError_t launch_reset(const TravParams& p, hipStream_t s);
 hipError_t launch_admit(const TravParams& p, hipStream_t s);
 hipError_t launch_slot_hist(const TravParams& p, uint32_t* live, hipStream_t s);
+// The part of a serving step after its traversal launch: report head and
+// round advance, per-slot live counts, completion flags, FP64 re-evaluation
+// of the slots that completed (results in p.res).  Every launch has a fixed
+// shape, so the sequence can be replayed from a graph.
+hipError_t launch_step_tail(const TravParams& p, StepHead* head, uint32_t* live, uint32_t* finish, hipStream_t s);
+// Adds a root kernel node for a traversal launch with the cooperative attribute.
+hipError_t add_traverse_node(hipGraph_t g, const TravParams& p, uint32_t blocks, uint32_t threads,
+                             hipGraphNode_t* node);
 
 // selfcheck.hip
 hipError_t launch_eval_bounds(uint32_t n, const float* a, const float* b, float* out, hipStream_t s);

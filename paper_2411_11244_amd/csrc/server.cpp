@@ -10,9 +10,16 @@
 //   2. traversal: the persistent kernel runs at most rounds_per_step rounds of
 //      every slot in flight (new slots join the running fronts);
 //   3. a per-slot histogram of the live front and leaf-pair entries;
-//   4. every slot with no live entries is complete: FP64 re-evaluation of its
-//      candidates, its result is copied back and queued for polling, and the
-//      slot is freed.
+//   4. every in-flight slot with no live entries is complete: the device flags
+//      it, re-evaluates its candidates in FP64 and takes it out of flight;
+//   5. one copy of the step's report (outcome, live counts, completion flags,
+//      results) to pinned host memory, then one host wait; completed results
+//      are queued for polling and their slots freed.
+// Steps 2-5 have a fixed shape: they are built once as a HIP graph (the
+// traversal as a cooperative kernel node, the rest captured from the stream)
+// and replayed every step; the round index that selects the buffer parity
+// lives on the device, so the replayed launches need no new arguments.  The
+// graph is rebuilt when the spill stack grows.
 // A spill-stack overflow puts every query in flight back at the head of the
 // queue (keeping its submit time), clears the traversal storage and halves the
 // concurrency limit; when a query overflows alone the stack doubles (up to
@@ -58,16 +65,23 @@ struct gdist_server {
   uint64_t stack_cap = 0;
   size_t box_stride = 0;  // floats of refitted boxes per slot
   uint32_t max_leaves = 0;
-  DevBuf desc, st, res, boxes, front[2], leaf[2], stack, counts, cand, cand64, ctl, live, list, tab;
+  DevBuf desc, st, boxes, front[2], leaf[2], stack, counts, cand, cand64, ctl, list, tab;
+  DevBuf rep;                 // step report: StepHead, live[S], finish[S], results[S]
+  size_t live_off = 0, fin_off = 0, res_off = 0, rep_bytes = 0;
+  void* rep_host = nullptr;   // pinned copy of the report
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec = nullptr;
+  TravParams gp{};            // the step parameters the graph (or the direct mode) was set up for
+  bool gp_set = false;
+  uint32_t graph_mode = 0;
   // slot table (worker thread only)
   std::vector<uint8_t> active;
   uint32_t fallbacks = 0;
   std::vector<Pending> slot_req;
   std::vector<uint32_t> free_slots;
-  uint32_t n_active = 0, round0 = 0, concurrency = 0, clean_steps = 0;
+  uint32_t n_active = 0, concurrency = 0, clean_steps = 0;
   uint64_t live_total = 0;
   // shared with the API threads
   std::mutex mu;
@@ -87,7 +101,7 @@ TravParams params(gdist_server* sv) {
   gdist_ctx* c = sv->c;
   p.desc = (const SlotDesc*)sv->desc.p;
   p.st = (SlotState*)sv->st.p;
-  p.res = (gdist_result_t*)sv->res.p;
+  p.res = (gdist_result_t*)((char*)sv->rep.p + sv->res_off);
   p.front[0] = (uint4*)sv->front[0].p;
   p.front[1] = (uint4*)sv->front[1].p;
   p.leaf[0] = (uint4*)sv->leaf[0].p;
@@ -112,7 +126,7 @@ TravParams params(gdist_server* sv) {
   p.expand_budget = c->expand_budget;
   p.k_cap = c->k_cap;
   p.spin_limit = 1u << 26;
-  p.round0 = sv->round0;
+  p.round0 = 0;   // the device keeps the round base across steps
   p.max_rounds = sv->cfg.rounds_per_step;
   p.cand_stop = 0;
   return p;
@@ -177,6 +191,63 @@ gdist_status_t reset_storage(gdist_server* sv) {
 }
 
 // Admit the queries of `reqs` into free slots (refit, dive, root pairs).
+// Steps 3-5 of a device step on the context's stream.
+hipError_t enqueue_tail(gdist_server* sv, const TravParams& p) {
+  char* rep = (char*)sv->rep.p;
+  hipStream_t s = sv->c->stream;
+  hipError_t e = launch_step_tail(p, (StepHead*)rep, (uint32_t*)(rep + sv->live_off), (uint32_t*)(rep + sv->fin_off), s);
+  if (e == hipSuccess) e = hipMemcpyAsync(sv->rep_host, rep, sv->rep_bytes, hipMemcpyDeviceToHost, s);
+  return e;
+}
+
+// Steps 2-5 launched one by one.
+hipError_t enqueue_step(gdist_server* sv, const TravParams& p) {
+  gdist_ctx* c = sv->c;
+  hipError_t e = launch_traverse(p, c->trav_blocks, c->trav_threads, c->stream);
+  return e == hipSuccess ? enqueue_tail(sv, p) : e;
+}
+
+void drop_graph(gdist_server* sv) {
+  if (sv->gexec) (void)hipGraphExecDestroy(sv->gexec);
+  sv->gexec = nullptr;
+  sv->graph_mode = 0;
+}
+
+// Build the step graph for parameters p: a cooperative kernel node for the
+// traversal, then the captured tail as a child graph (7 nodes: 6 kernels and
+// the report copy).  If the runtime refuses any part, the server launches the
+// step's kernels one by one instead (graph_mode 0).
+void build_graph(gdist_server* sv, const TravParams& p) {
+  gdist_ctx* c = sv->c;
+  drop_graph(sv);
+  sv->gp = p;
+  sv->gp_set = true;
+  if (sv->cfg.flags & GDIST_SERVER_DIRECT) return;
+  hipGraph_t g = nullptr, tail = nullptr;
+  hipGraphNode_t tn = nullptr, cn = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t e1 = enqueue_tail(sv, p);
+    hipError_t e2 = hipStreamEndCapture(c->stream, &tail);
+    e = e1 != hipSuccess ? e1 : e2;
+  }
+  size_t n_tail = 0;
+  if (e == hipSuccess) e = hipGraphGetNodes(tail, nullptr, &n_tail);
+  if (e == hipSuccess && n_tail != 7) e = hipErrorInvalidValue;
+  if (e == hipSuccess) e = hipGraphCreate(&g, 0);
+  if (e == hipSuccess) e = add_traverse_node(g, p, c->trav_blocks, c->trav_threads, &tn);
+  if (e == hipSuccess) e = hipGraphAddChildGraphNode(&cn, g, &tn, 1, tail);
+  if (e == hipSuccess) e = hipGraphInstantiate(&sv->gexec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (tail) (void)hipGraphDestroy(tail);
+  if (e == hipSuccess) {
+    sv->graph_mode = 1;
+  } else {
+    (void)hipGetLastError();
+    sv->gexec = nullptr;
+  }
+}
+
 gdist_status_t admit(gdist_server* sv, std::vector<Pending>& reqs) {
   gdist_ctx* c = sv->c;
   std::vector<uint32_t> slots;
@@ -232,6 +303,12 @@ gdist_status_t admit(gdist_server* sv, std::vector<Pending>& reqs) {
 // One device step.  Returns a non-OK status only for device failures.
 gdist_status_t step(gdist_server* sv) {
   gdist_ctx* c = sv->c;
+  // 0. the step graph follows the storage (the spill stack may have grown)
+  const TravParams p = params(sv);
+  if (!sv->gp_set || std::memcmp(&p, &sv->gp, sizeof(p)) != 0) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    build_graph(sv, p);
+  }
   // 1. admission
   std::vector<Pending> reqs;
   {
@@ -248,24 +325,29 @@ gdist_status_t step(gdist_server* sv) {
     if (s != GDIST_OK) return s;
   }
   if (sv->n_active == 0) return GDIST_OK;
-  // 2. traversal step
-  TravParams p = params(sv);
-  Ctl hctl;
+  // 2-5. traversal, live counts, completion, re-evaluation, report copy
   HIPCHK(hipEventRecord(sv->ev[0], c->stream));
-  HIPCHK(launch_traverse(p, c->trav_blocks, c->trav_threads, c->stream));
+  if (sv->gexec) HIPCHK(hipGraphLaunch(sv->gexec, c->stream));
+  else HIPCHK(enqueue_step(sv, p));
   HIPCHK(hipEventRecord(sv->ev[1], c->stream));
-  HIPCHK(hipMemcpyAsync(&hctl, sv->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, sv->ev[0], sv->ev[1]));
+  const char* rep = (const char*)sv->rep_host;
+  StepHead head;
+  std::memcpy(&head, rep, sizeof(head));
+  const uint32_t* live = (const uint32_t*)(rep + sv->live_off);
+  const uint32_t* finish = (const uint32_t*)(rep + sv->fin_off);
+  const gdist_result_t* res = (const gdist_result_t*)(rep + sv->res_off);
   {
     std::lock_guard<std::mutex> g(sv->mu);
     sv->stats.steps++;
-    sv->stats.rounds += hctl.rounds_done;
+    sv->stats.rounds += head.rounds_done;
     sv->stats.device_ms += ms;
+    if (sv->gexec) sv->stats.graph_steps++;
   }
-  if (hctl.abort) return fail(GDIST_E_DEVICE, "server step: grid barrier timed out");
-  if (hctl.overflow & 11u) {
+  if (head.abort) return fail(GDIST_E_DEVICE, "server step: grid barrier timed out");
+  if (head.overflow) {
     // pending pairs were lost: every query in flight starts over later
     std::vector<uint32_t> act;
     for (uint32_t s = 0; s < sv->S; ++s)
@@ -293,50 +375,28 @@ gdist_status_t step(gdist_server* sv) {
     sv->clean_steps = 0;
     return reset_storage(sv);
   }
-  sv->round0 += hctl.rounds_done;
-  // 3. live entries per slot
-  p = params(sv);
-  HIPCHK(hipMemsetAsync(sv->live.p, 0, 4ull * sv->S, c->stream));
-  HIPCHK(launch_slot_hist(p, (uint32_t*)sv->live.p, c->stream));
-  std::vector<uint32_t> live(sv->S);
-  std::vector<SlotState> hst(sv->S);
-  HIPCHK(hipMemcpyAsync(live.data(), sv->live.p, 4ull * sv->S, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(hst.data(), sv->st.p, sizeof(SlotState) * sv->S, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  // 4. completions
+  // completions: the device flagged exactly the in-flight slots that drained
   std::vector<uint32_t> fin, bad;
   uint64_t total = 0;
   for (uint32_t s = 0; s < sv->S; ++s) {
+    const bool drained = sv->active[s] && live[s] == 0;
+    if (finish[s] > 2u || (finish[s] != 0u) != drained)
+      return fail(GDIST_E_DEVICE, "server step: completion flags disagree with the slot table (slot %u)", s);
     if (!sv->active[s]) continue;
     total += live[s];
-    if (live[s] != 0) continue;
-    if (hst[s].cand_overflow) bad.push_back(s);
-    else fin.push_back(s);
+    if (finish[s] == 1u) fin.push_back(s);
+    else if (finish[s] == 2u) bad.push_back(s);
   }
   sv->live_total = total;
   if (++sv->clean_steps > 16 && sv->concurrency < sv->S) {
     sv->concurrency++;
     sv->clean_steps = 0;
   }
-  for (uint32_t s : bad) run_alone(sv, sv->slot_req[s]);
-  if (!fin.empty()) {
-    char* stage = (char*)sv->pinned;
-    const size_t list_off = sizeof(SlotDesc) * sv->S;
-    std::memcpy(stage + list_off, fin.data(), 4 * fin.size());
-    HIPCHK(hipMemcpyAsync(sv->list.p, stage + list_off, 4 * fin.size(), hipMemcpyHostToDevice, c->stream));
-    p = params(sv);
-    p.n_list = (uint32_t)fin.size();
-    HIPCHK(launch_reeval(p, c->stream));
-    std::vector<gdist_result_t> out(fin.size());
-    for (size_t i = 0; i < fin.size(); ++i)
-      HIPCHK(hipMemcpyAsync(&out[i], (gdist_result_t*)sv->res.p + fin[i], sizeof(gdist_result_t),
-                            hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
-    for (size_t i = 0; i < fin.size(); ++i) {
-      const Pending& rq = sv->slot_req[fin[i]];
-      complete(sv, rq.tag, rq.t_submit, out[i]);
-    }
+  for (uint32_t s : fin) {
+    const Pending& rq = sv->slot_req[s];
+    complete(sv, rq.tag, rq.t_submit, res[s]);
   }
+  for (uint32_t s : bad) run_alone(sv, sv->slot_req[s]);
   for (uint32_t s : bad) fin.push_back(s);
   for (uint32_t s : fin) {
     sv->active[s] = 0;
@@ -376,11 +436,13 @@ void worker_main(gdist_server* sv) {
 
 void free_server(gdist_server* sv) {
   gdist_ctx* c = sv->c;
-  DevBuf* bufs[] = {&sv->desc,    &sv->st,     &sv->res,   &sv->boxes,  &sv->front[0], &sv->front[1],
-                    &sv->leaf[0], &sv->leaf[1], &sv->stack, &sv->counts, &sv->cand,     &sv->cand64,
-                    &sv->ctl,     &sv->live,    &sv->list,  &sv->tab};
+  drop_graph(sv);
+  DevBuf* bufs[] = {&sv->desc,  &sv->st,     &sv->rep,    &sv->boxes, &sv->front[0], &sv->front[1],
+                    &sv->leaf[0], &sv->leaf[1], &sv->stack, &sv->counts, &sv->cand,    &sv->cand64,
+                    &sv->ctl,   &sv->list,   &sv->tab};
   for (DevBuf* b : bufs) release_buf(c, *b);
   if (sv->pinned) (void)hipHostFree(sv->pinned);
+  if (sv->rep_host) (void)hipHostFree(sv->rep_host);
   for (int i = 0; i < 2; ++i)
     if (sv->ev[i]) (void)hipEventDestroy(sv->ev[i]);
 }
@@ -429,9 +491,13 @@ gdist_status_t gdist_server_start(gdist_ctx_t c, const gdist_server_config_t* co
   auto A = [&](DevBuf& b, size_t bytes) {
     if (s == GDIST_OK) s = ensure(c, b, bytes);
   };
+  sv->live_off = sizeof(StepHead);
+  sv->fin_off = sv->live_off + 4ull * sv->S;
+  sv->res_off = (sv->fin_off + 4ull * sv->S + 255) & ~(size_t)255;
+  sv->rep_bytes = sv->res_off + sizeof(gdist_result_t) * sv->S;
   A(sv->desc, sizeof(SlotDesc) * sv->S);
   A(sv->st, sizeof(SlotState) * sv->S);
-  A(sv->res, sizeof(gdist_result_t) * sv->S);
+  A(sv->rep, sv->rep_bytes);
   A(sv->boxes, sizeof(float) * sv->box_stride * sv->S);
   for (int b = 0; b < 2; ++b) {
     A(sv->front[b], 16ull * fcap);
@@ -442,14 +508,13 @@ gdist_status_t gdist_server_start(gdist_ctx_t c, const gdist_server_config_t* co
   A(sv->cand, sizeof(Cand) * (size_t)sv->cps * sv->S);
   A(sv->cand64, sizeof(double) * (size_t)sv->cps * sv->S);
   A(sv->ctl, sizeof(Ctl));
-  A(sv->live, 4ull * sv->S);
   A(sv->list, 4ull * sv->S);
   A(sv->tab, sizeof(RefitJob) * sv->S + sizeof(ReduceJob) * sv->S * kMaxRefitPasses + 256);
   if (s == GDIST_OK) {
     sv->pinned_bytes = tab_offset(sv) + sv->tab.bytes;
-    if (hipHostMalloc(&sv->pinned, sv->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&sv->pinned, sv->pinned_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&sv->rep_host, sv->rep_bytes, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
-      sv->pinned = nullptr;
       s = fail(GDIST_E_OOM, "hipHostMalloc for the server failed");
     }
   }
@@ -457,6 +522,7 @@ gdist_status_t gdist_server_start(gdist_ctx_t c, const gdist_server_config_t* co
     s = fail(GDIST_E_DEVICE, "hipEventCreate failed");
   if (s == GDIST_OK) s = reset_storage(sv);
   if (s == GDIST_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = fail(GDIST_E_DEVICE, "server reset failed");
+  if (s == GDIST_OK) build_graph(sv, params(sv));
   if (s != GDIST_OK) {
     std::string msg = gdist_last_error();
     free_server(sv);
@@ -509,6 +575,7 @@ gdist_status_t gdist_server_stats(gdist_server_t sv, gdist_server_stats_t* out) 
   out->pending = (uint32_t)sv->pending.size();
   out->concurrency = sv->concurrency;
   out->fallbacks = sv->fallbacks;
+  out->graph_mode = sv->graph_mode;
   return GDIST_OK;
 }
 

@@ -36,6 +36,8 @@
 // lower - delta > best, the best is improved only with upper + delta, and a
 // triangle pair becomes a candidate when d32 - delta <= best.  Max mode is the
 // mirror image (Sec. 3: the maximum is computed symmetrically).
+#include <cstring>
+
 #include "internal.hpp"
 
 namespace gd {
@@ -213,7 +215,8 @@ __device__ __forceinline__ float sep_lower(const V3<float>* P, const V3<float>* 
   return lb;
 }
 
-// Zero the control block and the segment counts of the first round's buffers.
+// Zero the control block and the segment counts of the first round's buffers;
+// no slot is in flight afterwards.
 __global__ void k_reset(TravParams p) {
   uint32_t* w = reinterpret_cast<uint32_t*>(p.ctl);
   for (uint32_t i = threadIdx.x; i < sizeof(Ctl) / 4; i += blockDim.x) w[i] = 0u;
@@ -222,6 +225,7 @@ __global__ void k_reset(TravParams p) {
     p.fcount[cur][i] = 0u;
     p.lcount[cur][i] = 0u;
   }
+  for (uint32_t i = threadIdx.x; i < p.n_slots; i += blockDim.x) p.st[i].active = 0u;
 }
 
 // One wave per admitted query: error window, root bounds, greedy dive, and
@@ -315,6 +319,7 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
     st.n_admitted = 0;
     st.n_cand = 0;
     st.cand_overflow = 0;
+    st.active = 1u;
     st.key_pair = ~0ull;
     st.best = fbits(best);
     st.best32 = mode == 0 ? fbits(__builtin_huge_valf()) : 0u;
@@ -323,7 +328,7 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
     r.status = GDIST_E_DEVICE;
     r.flags = 0;
     // root pairs enter the next round through the admission segment
-    const uint32_t cur = p.round0 & 1u, nb = p.nblocks;
+    const uint32_t cur = (p.round0 + p.ctl->round_base) & 1u, nb = p.nblocks;
     uint4 e = make_uint4(1u, 1u, fbits(key), s);
     if (d.LA == 1 && d.LB == 1) {
       uint32_t i = atomicAdd(&p.lcount[cur][nb], 1u);
@@ -758,10 +763,13 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   }
   if (lds_slots)
     for (uint32_t s = tid; s < p.n_slots; s += kTravBlock) bs->delta[s] = p.st[s].delta;
+  // nothing in this launch writes round_base (the next stepped launch's base
+  // is advanced by a later kernel)
+  const uint32_t round0 = p.round0 + c->round_base;
 
   for (uint32_t r = 0; r < p.max_rounds; ++r) {
     if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) break;
-    const uint32_t round = p.round0 + r;   // global round: selects the buffer parity
+    const uint32_t round = round0 + r;     // global round: selects the buffer parity
     Round rd;
     rd.nb = gridDim.x + 1u;                // workgroup segments + the admission segment
     rd.seg_f = p.seg_front;
@@ -879,11 +887,13 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
 //    in the world frame from the caller's FP32 vertices and FP64 poses.
 struct ReevalRange {
   uint32_t slot, begin, stride, end;
+  bool skip;   // the slot does not complete in this launch
 };
 __device__ __forceinline__ ReevalRange reeval_range(const TravParams& p, uint32_t G) {
   ReevalRange r;
   const uint32_t i = blockIdx.x / G, part = blockIdx.x % G;
   r.slot = p.slot_list ? p.slot_list[i] : i;
+  r.skip = p.finish && p.finish[r.slot] != 1u;
   uint32_t n = p.st[r.slot].n_cand;
   r.end = n < p.cand_per_slot ? n : p.cand_per_slot;
   r.begin = part * kTravThreads + threadIdx.x;
@@ -895,6 +905,7 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_values(TravParams p, ui
   Ctl* c = p.ctl;
   if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) return;
   const ReevalRange rr = reeval_range(p, G);
+  if (rr.skip) return;
   const SlotDesc& d = p.desc[rr.slot];
   SlotState& st = p.st[rr.slot];
   const Cand* cands = p.cand + (uint64_t)rr.slot * p.cand_per_slot;
@@ -931,6 +942,7 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_ties(TravParams p, uint
   Ctl* c = p.ctl;
   if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) return;
   const ReevalRange rr = reeval_range(p, G);
+  if (rr.skip) return;
   const SlotDesc& d = p.desc[rr.slot];
   SlotState& st = p.st[rr.slot];
   const Cand* cands = p.cand + (uint64_t)rr.slot * p.cand_per_slot;
@@ -951,6 +963,7 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_report(TravParams p, ui
   Ctl* c = p.ctl;
   if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) return;
   const ReevalRange rr = reeval_range(p, G);
+  if (rr.skip) return;
   const SlotDesc& d = p.desc[rr.slot];
   const SlotState& st = p.st[rr.slot];
   const Cand* cands = p.cand + (uint64_t)rr.slot * p.cand_per_slot;
@@ -991,14 +1004,15 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_report(TravParams p, ui
 }
 
 // Live entries per slot in the current front and leaf buffers and on the
-// spill stack (after a step): workgroup b counts segment b of each (the last
+// spill stack (after a step, whose launch advanced round_base): workgroup b counts segment b of each (the last
 // workgroup the admission segment) and its grid-stride share of the stack in
 // LDS, and adds its non-zero counts to live[].
 __global__ __launch_bounds__(kTravThreads) void k_slot_hist(TravParams p, uint32_t* __restrict__ live) {
   __shared__ uint32_t h[kLdsSlots];
+  if (p.ctl->abort || p.ctl->overflow) return;   // the storage is reset instead
   for (uint32_t i = threadIdx.x; i < p.n_slots; i += kTravThreads) h[i] = 0u;
   __syncthreads();
-  const uint32_t cur = p.round0 & 1u, b = blockIdx.x;
+  const uint32_t cur = (p.round0 + p.ctl->round_base) & 1u, b = blockIdx.x;
   const uint32_t nf = p.fcount[cur][b], nl = p.lcount[cur][b];
   const uint4* fs = p.front[cur] + (uint64_t)b * p.seg_front;
   const uint4* ls = p.leaf[cur] + (uint64_t)b * p.seg_leaf;
@@ -1010,6 +1024,39 @@ __global__ __launch_bounds__(kTravThreads) void k_slot_hist(TravParams p, uint32
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < p.n_slots; i += kTravThreads)
     if (h[i]) atomicAdd(&live[i], h[i]);
+}
+
+// Serving step, after its traversal launch: copy the launch's outcome into
+// the step report, advance the round base past the rounds it ran, clear the
+// per-slot live counts.
+__global__ void k_step_advance(TravParams p, StepHead* __restrict__ head, uint32_t* __restrict__ live) {
+  Ctl* c = p.ctl;
+  if (threadIdx.x == 0) {
+    const uint32_t ov = c->overflow, ab = c->abort, rd = c->rounds_done;
+    head->overflow = ov;
+    head->abort = ab;
+    head->rounds_done = rd;
+    if (!ov && !ab) c->round_base += rd;
+  }
+  for (uint32_t i = threadIdx.x; i < p.n_slots; i += blockDim.x) live[i] = 0u;
+}
+
+// Serving step completion: an in-flight slot without live entries has
+// drained.  finish = 1: re-evaluate it now; 2: its candidate region filled
+// up (the host re-runs the query alone); 0: still running or idle.  A
+// drained slot leaves flight.  Nothing completes after an overflow or abort.
+__global__ void k_step_select(TravParams p, const StepHead* __restrict__ head, const uint32_t* __restrict__ live,
+                              uint32_t* __restrict__ finish) {
+  const bool stop = head->overflow || head->abort;
+  for (uint32_t s = threadIdx.x; s < p.n_slots; s += blockDim.x) {
+    SlotState& st = p.st[s];
+    uint32_t f = 0u;
+    if (!stop && st.active && live[s] == 0u) {
+      f = st.cand_overflow ? 2u : 1u;
+      st.active = 0u;
+    }
+    finish[s] = f;
+  }
 }
 
 uint32_t reeval_groups(uint32_t n_list) {
@@ -1060,6 +1107,37 @@ hipError_t launch_traverse(const TravParams& p, uint32_t blocks, uint32_t thread
   void* args[] = {&pp};
   const void* fn = p.n_slots <= kLdsSlots ? (const void*)k_traverse<true> : (const void*)k_traverse<false>;
   return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(threads), args, 0, s);
+}
+
+// Graph node of a traversal launch, marked cooperative like launch_traverse.
+hipError_t add_traverse_node(hipGraph_t g, const TravParams& p, uint32_t blocks, uint32_t threads,
+                             hipGraphNode_t* node) {
+  TravParams pp = p;
+  void* args[] = {&pp};
+  hipKernelNodeParams kp;
+  std::memset(&kp, 0, sizeof(kp));
+  kp.func = p.n_slots <= kLdsSlots ? (void*)k_traverse<true> : (void*)k_traverse<false>;
+  kp.gridDim = dim3(blocks);
+  kp.blockDim = dim3(threads);
+  kp.kernelParams = args;
+  hipError_t e = hipGraphAddKernelNode(node, g, nullptr, 0, &kp);
+  if (e != hipSuccess) return e;
+  hipKernelNodeAttrValue v;
+  std::memset(&v, 0, sizeof(v));
+  v.cooperative = 1;
+  return hipGraphKernelNodeSetAttribute(*node, hipKernelNodeAttributeCooperative, &v);
+}
+
+hipError_t launch_step_tail(const TravParams& p, StepHead* head, uint32_t* live, uint32_t* finish, hipStream_t s) {
+  if (p.n_slots > kLdsSlots) return hipErrorInvalidValue;
+  k_step_advance<<<1, 256, 0, s>>>(p, head, live);
+  k_slot_hist<<<p.nblocks + 1, kTravThreads, 0, s>>>(p, live);
+  k_step_select<<<1, 512, 0, s>>>(p, head, live, finish);
+  TravParams q = p;
+  q.slot_list = nullptr;
+  q.n_list = p.n_slots;
+  q.finish = finish;
+  return launch_reeval(q, s);
 }
 
 hipError_t launch_reeval(const TravParams& p, hipStream_t s) {

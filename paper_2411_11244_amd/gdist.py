@@ -22,6 +22,7 @@ GDIST_OK, GDIST_E_INVALID, GDIST_E_HANDLE, GDIST_E_OOM, GDIST_E_CAPACITY, GDIST_
 STATUS_NAMES = ["OK", "E_INVALID", "E_HANDLE", "E_OOM", "E_CAPACITY", "E_DEVICE", "E_BUSY"]
 GDIST_BUILD_DEVICE_PTR = 1
 GDIST_F_TIED, GDIST_F_ZERO = 1, 2
+GDIST_SERVER_DIRECT = 1
 
 
 class GdistError(RuntimeError):
@@ -72,7 +73,7 @@ class gdist_stats_t(C.Structure):
 
 class gdist_server_config_t(C.Structure):
     _fields_ = [("max_slots", C.c_uint32), ("rounds_per_step", C.c_uint32), ("front_capacity", C.c_uint64),
-                ("cand_per_slot", C.c_uint32), ("max_tris", C.c_uint32), ("reserved", C.c_uint32),
+                ("cand_per_slot", C.c_uint32), ("max_tris", C.c_uint32), ("flags", C.c_uint32),
                 ("stack_capacity", C.c_uint64)]
 
 
@@ -85,7 +86,8 @@ class gdist_server_stats_t(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("submitted", "admitted", "completed", "failed", "requeued",
                                           "steps", "rounds")] + \
                [(n, C.c_uint32) for n in ("active", "pending", "concurrency", "fallbacks")] + \
-               [("device_ms", C.c_double)]
+               [("device_ms", C.c_double), ("graph_steps", C.c_uint64), ("graph_mode", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -347,8 +349,9 @@ def gdist_eval_tri_tri(ctx: int, p, q, mode: int = 0):
 
 # ------------------------------------------------------------------ serving
 def gdist_server_start(ctx: int, max_slots: int = 0, rounds_per_step: int = 0, front_capacity: int = 0,
-                       cand_per_slot: int = 0, max_tris: int = 0, stack_capacity: int = 0) -> int:
-    cfg = gdist_server_config_t(max_slots, rounds_per_step, front_capacity, cand_per_slot, max_tris, 0,
+                       cand_per_slot: int = 0, max_tris: int = 0, stack_capacity: int = 0,
+                       flags: int = 0) -> int:
+    cfg = gdist_server_config_t(max_slots, rounds_per_step, front_capacity, cand_per_slot, max_tris, flags,
                                 stack_capacity)
     h = C.c_void_p()
     _check(lib().gdist_server_start(ctx, C.byref(cfg), C.byref(h)))

@@ -24,13 +24,15 @@ from . import gdist
 
 def run_stream(ctx: int, handles: Sequence[int], queries, max_slots: int = 64, rounds_per_step: int = 4,
                front_capacity: int = 0, cand_per_slot: int = 0, time_scale: float = 1.0,
-               timeout_s: float = 300.0, stack_capacity: int = 0) -> dict:
+               timeout_s: float = 300.0, stack_capacity: int = 0, direct: bool = False) -> dict:
     """Submit ``queries`` (meshgen.Query with .arrival seconds) at their arrival
     times (scaled by ``time_scale``; 0 submits everything at once) and collect
     every completion.  Returns {"results": [dict per query, in query order],
-    "latency_ms": np.ndarray, "wall_s": float, "stats": server stats}."""
+    "latency_ms": np.ndarray, "wall_s": float, "stats": server stats}.
+    ``direct`` launches each step's kernels one by one instead of replaying
+    the step graph."""
     srv = gdist.gdist_server_start(ctx, max_slots, rounds_per_step, front_capacity, cand_per_slot, 0,
-                                   stack_capacity)
+                                   stack_capacity, gdist.GDIST_SERVER_DIRECT if direct else 0)
     n = len(queries)
     results: List[dict] = [None] * n  # type: ignore
     got = 0
@@ -71,13 +73,14 @@ def main(argv=None) -> int:
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--rounds", type=int, default=4)
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--direct", action="store_true", help="launch each step's kernels one by one (no graph)")
     a = ap.parse_args(argv)
     pool = g.serving_pool(a.seed, a.pool, a.tmin, a.tmax)
     qs = g.serving_stream(pool, a.rate, a.queries, seed=a.seed + 1)
     ctx = gdist.gdist_create(0)
     try:
         handles = [gdist.gdist_build(ctx, m.verts, m.tris) for m in pool]
-        out = run_stream(ctx, handles, qs, a.slots, a.rounds)
+        out = run_stream(ctx, handles, qs, a.slots, a.rounds, direct=a.direct)
     finally:
         gdist.gdist_destroy(ctx)
     lat = out["latency_ms"]

@@ -5,6 +5,11 @@ completed when its own traversal drains, must give exactly what gdist_query
 gives for it alone: same FP64 distance bits, same pair, same tie count (the
 FP64 re-evaluation decides all three from candidates that the conservative
 FP32 window never drops).  A sample is also checked against the FP64 oracle.
+
+Each device step after admission is replayed from a HIP graph (every step of
+a run is one replay, with the admission's launches and host work between
+replays); the same stream with the kernels launched one by one
+(GDIST_SERVER_DIRECT) must give the same results.
 """
 import numpy as np
 import pytest
@@ -47,15 +52,25 @@ def served(gctx):
         gdist.gdist_release(gctx, h)
 
 
-@pytest.mark.parametrize("slots,rounds,scale", [(8, 1, 0.0), (32, 3, 0.0), (64, 4, 1.0)])
-def test_server_equals_alone(gctx, served, slots, rounds, scale):
+def _graph_used(st, direct):
+    if direct:
+        assert st["graph_mode"] == 0 and st["graph_steps"] == 0
+    else:
+        assert st["graph_mode"] == 1 and st["graph_steps"] == st["steps"]
+
+
+@pytest.mark.parametrize("slots,rounds,scale,direct", [(8, 1, 0.0, False), (32, 3, 0.0, False), (64, 4, 1.0, False),
+                                                       (32, 3, 0.0, True)])
+def test_server_equals_alone(gctx, served, slots, rounds, scale, direct):
     pool, handles, qs, alone = served
-    out = run_stream(gctx, handles, qs, max_slots=slots, rounds_per_step=rounds, time_scale=scale, timeout_s=120)
+    out = run_stream(gctx, handles, qs, max_slots=slots, rounds_per_step=rounds, time_scale=scale, timeout_s=120,
+                     direct=direct)
     for r, a in zip(out["results"], alone):
         _same(r, a)
     st = out["stats"]
     assert st["submitted"] == len(qs) and st["completed"] == len(qs) and st["failed"] == 0
     assert st["steps"] >= 1 and st["rounds"] >= 1
+    _graph_used(st, direct)
     assert np.all(out["latency_ms"] >= 0)
 
 
@@ -82,6 +97,7 @@ def test_server_storage_growth(gctx, served):
     for r, a in zip(out["results"], alone[:24]):
         _same(r, a)
     assert out["stats"]["requeued"] > 0
+    _graph_used(out["stats"], False)   # rebuilt for the grown stack
 
 
 def test_server_candidate_overflow(gctx):
