@@ -239,9 +239,10 @@ typedef struct gdist_server* gdist_server_t;
 /* A device step is a fixed launch sequence after admission: the traversal
  * (at most rounds_per_step rounds), per-slot live counts, completion flags,
  * FP64 re-evaluation of the completed slots, one copy of the step's report to
- * pinned host memory.  By default the server captures it once as a HIP graph
- * and replays it every step (one graph launch and one host wait per step);
- * with this flag it launches the kernels one by one (same results). */
+ * pinned host memory.  By default the server builds it once as a HIP graph
+ * (again after the spill stack grows) and replays it every step: one graph
+ * launch and one host wait per step.  With this flag it launches the kernels
+ * one by one (same results). */
 #define GDIST_SERVER_DIRECT 1u
 
 typedef struct {
@@ -276,8 +277,8 @@ typedef struct {
   uint32_t fallbacks;       /* queries re-run alone through gdist_query's growing storage */
   double device_ms;         /* device time of all steps' launch sequences (HIP events)    */
   uint64_t graph_steps;     /* steps replayed from the captured graph                     */
-  uint32_t graph_mode;      /* 0: kernels launched one by one; 1: stream-captured graph;
-                               2: graph with an explicit cooperative traversal node      */
+  uint32_t graph_mode;      /* 1: steps replay the step graph; 0: kernels launched one by
+                               one (GDIST_SERVER_DIRECT, or the runtime refused the graph) */
   uint32_t reserved;
 } gdist_server_stats_t;
 
