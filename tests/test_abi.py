@@ -49,3 +49,36 @@ def test_no_device_fails_loudly():
     from paper_2411_11244_amd import gdist
     with pytest.raises(gdist.GdistError):
         gdist.gdist_create(0)
+
+
+STRUCTS = ("gdist_pose_t", "gdist_result_t", "gdist_query_desc_t", "gdist_mesh_info_t", "gdist_stats_t",
+           "gdist_server_config_t", "gdist_completion_t", "gdist_server_stats_t")
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    """Every struct of the header has the size and field offsets the binding
+    assumes (the header compiled as C by gcc)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    from paper_2411_11244_amd import gdist
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gdist.h"', "int main(void) {"]
+    for name in STRUCTS:
+        ct = getattr(gdist, name)
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in ct._fields_:
+            lines.append(f'  printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                         text=True).stdout.splitlines())
+    for name in STRUCTS:
+        ct = getattr(gdist, name)
+        assert int(got[name]) == ctypes.sizeof(ct), name
+        for f, _ in ct._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(ct, f).offset, (name, f)
