@@ -35,7 +35,8 @@ struct SlotDesc {
 struct SlotState {
   uint32_t best;             // float bits: min mode = upper bound of D_min (+delta),
                              // max mode = lower bound of D_max (-delta)
-  uint32_t best32;           // float bits of the FP32 narrow-phase optimum
+  uint32_t best32;           // float bits of the FP32 narrow-phase optimum (the best candidate
+                             // value, taken at re-evaluation)
   float delta;               // FP32 error window
   uint32_t n_ties;
   unsigned long long key_d;  // double bits of the FP64 optimum

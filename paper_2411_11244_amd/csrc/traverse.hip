@@ -606,10 +606,33 @@ __device__ __forceinline__ void spill_wave(const BlockState* bs, const Round& rd
   if (j < rd.n_spill) rd.stk[(uint64_t)rd.st + j] = rd.fin[addr];
 }
 
+// Append a candidate triangle pair (d32 within the window of the slot's
+// bound) to the slot's region; rare, so one atomic per candidate.
+__device__ __forceinline__ void add_candidate(const TravParams& p, uint32_t slot, uint32_t pa, uint32_t pb, float dd) {
+  uint32_t idx = atomicAdd(&p.st[slot].n_cand, 1u);
+  if (idx < p.cand_per_slot) {
+    Cand ce;
+    ce.d32 = dd;
+    ce.slot = slot;
+    ce.ia = pa;
+    ce.ib = pb;
+    p.cand[(uint64_t)slot * p.cand_per_slot + idx] = ce;
+  } else {
+    atomicOr(&p.st[slot].cand_overflow, 1u);
+    if (p.cand_stop) atomicOr(&p.ctl->overflow, 4u);
+  }
+}
+
 // Narrow phase, stage 1: one lane per leaf pair.  The lane loads the leaf
-// pair's 1-2 triangles of each side once, gives each of the (up to 4)
-// triangle pairs the cheap separating-axis test, and pushes the survivors
-// onto the wave's LDS queue (at most 4 x 64 per call).
+// pair's 1-2 triangles of each side once.  Min mode: each of the (up to 4)
+// triangle pairs gets the cheap separating-axis test, and the survivors go
+// onto the wave's LDS queue (at most 4 x 64 per call) for the exact test.
+// Max mode: the exact value (the largest of the 9 vertex-pair distances) costs
+// no more than a filter, so the lane takes it here, improves the slot's bound
+// with its best value and appends its candidates; no max-mode pair is queued.
+// (A queued pair costs an LDS round trip and, in a batch, per-lane loads of
+// its slot's fields and per-lane atomics on the slot's bound; every max-mode
+// pair would pay them.)
 // The leaf-pair entries [base, base + 64) of the current round (lane order);
 // lanes past n_items get an inactive placeholder.
 __device__ __forceinline__ uint4 leaf_row(const BlockState* bs, const Round& rd, uint32_t base, uint32_t n_items,
@@ -639,7 +662,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
     leaf_range(ent.y, v.depthB, v.nB, sb, eb);
   }
   V3<float> P[2][3], Q[2][3];
-  if (act && mode == 0) {
+  if (act) {
     const Xf32& T = p.desc[slot].T;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -655,24 +678,40 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
       }
     }
   }
+  const bool any_max = __ballot(act && mode != 0) != 0ull;   // wave-uniform
+  float imp = 0.f;   // max mode: the lane's best improvement of the bound
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4) {
     const uint32_t pa = sa + (s4 & 1), pb = sb + (s4 >> 1);
     const bool valid = act && pa < ea && pb < eb;
-    bool pass = valid;
-    if (valid && mode == 0) pass = sep_lower(P[s4 & 1], Q[s4 >> 1]) - delta <= best;
+    bool pass = valid && mode == 0;
+    if (pass) pass = sep_lower(P[s4 & 1], Q[s4 >> 1]) - delta <= best;
     add_stat(ws, ST_TRI, valid);
+    if (any_max) {
+      const bool full = valid && mode != 0;
+      bool cand = false;
+      float dd = 0.f;
+      if (full) {
+        dd = sqrtf(tri_tri_max_d2<float, false>(P[s4 & 1], Q[s4 >> 1], nullptr, nullptr));
+        imp = fmaxf(imp, fmaxf(dd - delta, 0.f));
+        cand = dd + delta >= best;
+      }
+      if (cand) add_candidate(p, slot, pa, pb, dd);
+      add_stat(ws, ST_FULL, full);
+      add_stat(ws, ST_CAND, cand);
+    }
     uint64_t m = __ballot(pass);
     if (pass) q[qn + (uint32_t)__popcll(m & lt)] = make_uint4(slot, pa, pb, 0u);
     qn += (uint32_t)__popcll(m);
   }
   __builtin_amdgcn_wave_barrier();
+  if (any_max) improve_best(p, bs, rd.lds_slots, act && mode != 0 && imp > best, slot, mode, imp, lane);
 }
 
-// Narrow phase, stage 2: exact FP32 triangle-triangle distance on queued pairs.
+// Narrow phase, stage 2: exact FP32 triangle-triangle distance on queued pairs
+// (the filter queues min-mode pairs only).
 __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs, bool lds, uint4 e, bool act,
                                             uint32_t lane, uint64_t lt, WaveStats& ws) {
-  Ctl* c = p.ctl;
   const uint32_t slot = e.x, pa = e.y, pb = e.z;
   const SlotView v = slot_view(p, bs, lds, act, slot);
   const uint32_t mode = v.mode;
@@ -703,21 +742,7 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
     }
   }
   add_stat(ws, ST_FULL, act);
-  if (act && cand) {
-    // candidates are rare: one atomic per candidate on its slot's counter
-    uint32_t idx = atomicAdd(&p.st[slot].n_cand, 1u);
-    if (idx < p.cand_per_slot) {
-      Cand ce;
-      ce.d32 = dd;
-      ce.slot = slot;
-      ce.ia = pa;
-      ce.ib = pb;
-      p.cand[(uint64_t)slot * p.cand_per_slot + idx] = ce;
-    } else {
-      atomicOr(&p.st[slot].cand_overflow, 1u);
-      if (p.cand_stop) atomicOr(&c->overflow, 4u);
-    }
-  }
+  if (act && cand) add_candidate(p, slot, pa, pb, dd);
   add_stat(ws, ST_CAND, act && cand);
   improve_best(p, bs, lds, act, slot, mode, improve, lane);
   improve_bound(&p.st[0].best32, sizeof(SlotState) / 4, act, slot, mode, dd, lane);
@@ -913,6 +938,10 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_values(TravParams p, ui
   const float best = bitsf(ld_rlx(&st.best));
   for (uint32_t i = rr.begin; i < rr.end; i += rr.stride) {
     Cand cd = cands[i];
+    // the FP32 optimum over the tested triangle pairs is the best candidate
+    // value (max mode tests its pairs in the filter, which keeps no optimum)
+    if (d.mode == 0) atomicMin(&st.best32, fbits(cd.d32));
+    else atomicMax(&st.best32, fbits(cd.d32));
     const bool adm = d.mode == 0 ? (cd.d32 - st.delta <= best) : (cd.d32 + st.delta >= best);
     if (!adm) {
       d64[i] = -1.0;
