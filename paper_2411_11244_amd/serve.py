@@ -4,9 +4,12 @@ Queries arrive as a Poisson stream (seeded; meshgen.serving_stream) over a
 pool of meshes whose sizes are log-uniform; each is submitted at its arrival
 time and the completions are polled as they come.  Reported: completed
 queries/s over the run, and p50/p99 of the latency from submit to the result
-in host memory (the server's own steady-clock stamps).
+in host memory (the server's own steady-clock stamps).  With --compare, the
+same queries are also run in the plain form (one gdist_query per query, back
+to back: queries/s and per-call latency) and as one gdist_query_batch call,
+and every served result is checked against its plain result.
 
-    python -m paper_2411_11244_amd.serve --rate 400 --queries 2000 --pool 16
+    python -m paper_2411_11244_amd.serve --rate 5000 --queries 2000 --pool 64 --compare
 
 All distance work runs in libgdist.so; this file only schedules submissions.
 """
@@ -74,6 +77,8 @@ def main(argv=None) -> int:
     ap.add_argument("--rounds", type=int, default=4)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--direct", action="store_true", help="launch each step's kernels one by one (no graph)")
+    ap.add_argument("--compare", action="store_true",
+                    help="also run the queries in the plain form and as one batch, and check the served results")
     a = ap.parse_args(argv)
     pool = g.serving_pool(a.seed, a.pool, a.tmin, a.tmax)
     qs = g.serving_stream(pool, a.rate, a.queries, seed=a.seed + 1)
@@ -81,6 +86,7 @@ def main(argv=None) -> int:
     try:
         handles = [gdist.gdist_build(ctx, m.verts, m.tris) for m in pool]
         out = run_stream(ctx, handles, qs, a.slots, a.rounds, direct=a.direct)
+        cmp = compare(ctx, handles, qs, out["results"]) if a.compare else None
     finally:
         gdist.gdist_destroy(ctx)
     lat = out["latency_ms"]
@@ -88,9 +94,37 @@ def main(argv=None) -> int:
     print(json.dumps({"completed_qps": round(len(qs) / out["wall_s"], 2), "ok": ok, "n": len(qs),
                       "p50_ms": round(float(np.percentile(lat, 50)), 3),
                       "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                      "offered_rate": a.rate, "pool": a.pool, "slots": a.slots,
-                      "rounds_per_step": a.rounds, "stats": out["stats"]}))
+                      "offered_rate": a.rate, "pool": a.pool, "pool_tris": sum(m.n_tris for m in pool),
+                      "slots": a.slots, "rounds_per_step": a.rounds, "stats": out["stats"], "compare": cmp}))
     return 0
+
+
+def compare(ctx: int, handles: Sequence[int], queries, served: List[dict]) -> dict:
+    """The same queries in the plain form (one gdist_query each, back to back)
+    and as one gdist_query_batch call; every served result must equal its
+    plain result (same FP64 distance bits and pair)."""
+    plain, lat = [], []
+    t0 = time.perf_counter()
+    for q in queries:
+        t = time.perf_counter()
+        plain.append(gdist.gdist_query(ctx, handles[q.a], handles[q.b], q.pose_a, q.pose_b, q.mode))
+        lat.append((time.perf_counter() - t) * 1e3)
+    plain_s = time.perf_counter() - t0
+    descs = [gdist.make_desc(handles[q.a], handles[q.b], q.pose_a, q.pose_b, q.mode) for q in queries]
+    gdist.gdist_query_batch(ctx, descs)   # warm: grows the batch storage once
+    t0 = time.perf_counter()
+    batch = gdist.gdist_query_batch(ctx, descs)
+    batch_s = time.perf_counter() - t0
+
+    def same(r, a):
+        return r["distance"] == a["distance"] and (r["tri_a"], r["tri_b"]) == (a["tri_a"], a["tri_b"])
+
+    lat = np.array(lat)
+    return {"plain_qps": round(len(queries) / plain_s, 2), "plain_p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "plain_p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "batch_qps": round(len(queries) / batch_s, 2), "batch_ms": round(batch_s * 1e3, 2),
+            "served_equal_plain": all(same(r, a) for r, a in zip(served, plain)),
+            "batch_equal_plain": all(same(r, a) for r, a in zip(batch, plain))}
 
 
 if __name__ == "__main__":
