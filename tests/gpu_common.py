@@ -31,7 +31,7 @@ def on_triangle(x, T, tol):
 
 
 def check_against_oracle(orc, r, ref, ma, pa, mb, pb, mode=0, abs_tol=1e-6, rel_tol=1e-5):
-    """The spec contract: distance within 1e-6 absolute or 1e-5
+    """The parity contract: distance within 1e-6 absolute or 1e-5
     relative; the reported pair is in the oracle's tie set (its own FP64
     distance within tau of the optimum) and equals the oracle's pair when the
     tie set has one element; the points lie on the reported triangles and
