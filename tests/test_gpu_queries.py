@@ -149,7 +149,9 @@ def test_symmetry_and_rigid_invariance(orc, gctx):
 
 
 def test_batch_equals_single(orc, gctx):
-    """Each result inside one batched launch equals the same query alone."""
+    """Each result inside one batched launch equals the same query alone,
+    including the FP32 optimum (the best candidate value) and the tie count;
+    the FP32 optimum lies within the FP32 error window of the FP64 result."""
     rng = np.random.default_rng(5)
     meshes = [g.random_mesh_of_size(rng, t) for t in (300, 2000, 5000, 800, 12000, 64)]
     hs = [build(gctx, m) for m in meshes]
@@ -167,6 +169,34 @@ def test_batch_equals_single(orc, gctx):
             assert s["distance"] == b["distance"]
             assert (s["tri_a"], s["tri_b"]) == (b["tri_a"], b["tri_b"])
             assert np.array_equal(s["point_a"], b["point_a"])
+            assert s["n_ties"] == b["n_ties"]
+            assert s["distance_fp32"] == b["distance_fp32"]
+            assert abs(b["distance_fp32"] - b["distance"]) <= 1e-4
+    finally:
+        for h in hs:
+            gdist.gdist_release(gctx, h)
+
+
+def test_mixed_batch_equals_single(orc, gctx):
+    """A batch drawn like the serving stream (random pairs and poses, half
+    max mode, a tenth overlapping): waves mix the slots of both modes.  Each
+    result equals the query alone; a sample matches the FP64 oracle."""
+    rng = np.random.default_rng(41)
+    pool = [g.random_mesh_of_size(rng, t) for t in (500, 3000, 20000, 1200, 8000, 150)]
+    hs = [build(gctx, m) for m in pool]
+    try:
+        qs = g.serving_stream(pool, 1000.0, 48, seed=42)
+        assert {q.mode for q in qs} == {0, 1}
+        batch = gdist.gdist_query_batch(gctx, [gdist.make_desc(hs[q.a], hs[q.b], q.pose_a, q.pose_b, q.mode)
+                                               for q in qs])
+        for i, (q, b) in enumerate(zip(qs, batch)):
+            s = gdist.gdist_query(gctx, hs[q.a], hs[q.b], q.pose_a, q.pose_b, q.mode)
+            assert s["distance"] == b["distance"] and s["n_ties"] == b["n_ties"]
+            assert (s["tri_a"], s["tri_b"]) == (b["tri_a"], b["tri_b"])
+            assert s["distance_fp32"] == b["distance_fp32"]
+            if i % 6 == 0:
+                ref = oracle_query(orc, pool[q.a], q.pose_a, pool[q.b], q.pose_b, q.mode)
+                check_against_oracle(orc, b, ref, pool[q.a], q.pose_a, pool[q.b], q.pose_b, q.mode)
     finally:
         for h in hs:
             gdist.gdist_release(gctx, h)
