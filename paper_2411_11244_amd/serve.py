@@ -73,8 +73,9 @@ def main(argv=None) -> int:
     ap.add_argument("--pool", type=int, default=16, help="meshes in the pool")
     ap.add_argument("--tmin", type=float, default=1e4)
     ap.add_argument("--tmax", type=float, default=2e6)
-    ap.add_argument("--slots", type=int, default=64)
-    ap.add_argument("--rounds", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=0, help="server slots (0: the tuning file's, else 64)")
+    ap.add_argument("--rounds", type=int, default=0, help="rounds per step (0: the tuning file's, else 4)")
+    ap.add_argument("--tuning", default="", help="tuning file written by tune.py --workload serving")
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--direct", action="store_true", help="launch each step's kernels one by one (no graph)")
     ap.add_argument("--compare", action="store_true",
@@ -84,6 +85,13 @@ def main(argv=None) -> int:
     qs = g.serving_stream(pool, a.rate, a.queries, seed=a.seed + 1)
     ctx = gdist.gdist_create(0)
     try:
+        tuned = {}
+        if a.tuning:
+            from . import tune
+            tune.apply(ctx, a.tuning)
+            tuned = tune.server_config(a.tuning)
+        a.slots = a.slots or tuned.get("max_slots", 64)
+        a.rounds = a.rounds or tuned.get("rounds_per_step", 4)
         handles = [gdist.gdist_build(ctx, m.verts, m.tris) for m in pool]
         out = run_stream(ctx, handles, qs, a.slots, a.rounds, direct=a.direct)
         cmp = compare(ctx, handles, qs, out["results"]) if a.compare else None

@@ -11,7 +11,15 @@ locality of the trees' boxes in the caches.
 
     python -m paper_2411_11244_amd.tune --out tune.json   (needs the GPU)
 
-``apply(ctx, path)`` sets the options stored in a tuning file on a context.
+For the serving core it sweeps the server's slots ("max_slots") and rounds
+per step ("rounds_per_step") together with the context options above, on a
+seeded stream of the serving mix submitted at once, and keeps the setting
+with the highest completed queries/s (every result must be OK):
+
+    python -m paper_2411_11244_amd.tune --workload serving --out serving.json
+
+``apply(ctx, path)`` sets the options stored in a tuning file on a context;
+``server_config(path)`` returns its server settings.
 """
 from __future__ import annotations
 
@@ -28,6 +36,7 @@ import numpy as np
 from . import gdist
 
 KEYS = ("expand_budget", "k_cap", "blocks_per_cu", "front_capacity", "group_size")
+SERVER_KEYS = ("max_slots", "rounds_per_step")
 
 
 def _set(ctx: int, k: str, v) -> None:
@@ -46,6 +55,16 @@ def apply(ctx: int, path_or_dict) -> Dict:
         if k in best:
             _set(ctx, k, best[k])
     return cfg
+
+
+def server_config(path_or_dict) -> Dict:
+    """The server settings (SERVER_KEYS) of a tuning file; empty if it has none."""
+    cfg = path_or_dict
+    if isinstance(path_or_dict, str):
+        with open(path_or_dict) as f:
+            cfg = json.load(f)
+    best = cfg.get("best", cfg)
+    return {k: int(best[k]) for k in SERVER_KEYS if k in best}
 
 
 def time_setting(ctx: int, descs: List, reps: int) -> float:
@@ -74,15 +93,58 @@ def tune(ctx: int, descs: List, grid: Dict[str, Iterable], reps: int = 3, log=pr
     return {"best": {k: best[k] for k in names}, "ms": best["ms"], "results": results}
 
 
+def tune_server(ctx: int, handles: List[int], queries, grid: Dict[str, Iterable], log=print) -> Dict:
+    """Sweep server and context settings on `queries` submitted at once; keep
+    the setting with the highest completed queries/s whose results are all OK."""
+    from .serve import run_stream
+    names = list(grid)
+    results = []
+    for values in itertools.product(*(grid[n] for n in names)):
+        setting = dict(zip(names, values))
+        for k, v in setting.items():
+            if k in KEYS:
+                _set(ctx, k, v)
+        out = run_stream(ctx, handles, queries, max_slots=int(setting.get("max_slots", 64)),
+                         rounds_per_step=int(setting.get("rounds_per_step", 4)), time_scale=0.0, timeout_s=300)
+        ok = all(r["status"] == gdist.GDIST_OK for r in out["results"])
+        qps = len(queries) / out["wall_s"]
+        results.append({**setting, "qps": qps, "p99_ms": float(np.percentile(out["latency_ms"], 99)), "ok": ok})
+        log(f"tune {setting} -> {qps:.1f} queries/s{'' if ok else ' (failures)'}")
+    good = [r for r in results if r["ok"]]
+    if not good:
+        raise RuntimeError("no server setting completed every query")
+    best = max(good, key=lambda r: r["qps"])
+    for k in names:
+        if k in KEYS:
+            _set(ctx, k, best[k])
+    return {"best": {k: best[k] for k in names}, "qps": best["qps"], "results": results}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="rings", choices=["rings", "tiny"])
+    ap.add_argument("--workload", default="rings", choices=["rings", "tiny", "serving"])
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--out", default="")
     ap.add_argument("--reps", type=int, default=3)
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import meshgen as g
+    if args.workload == "serving":
+        pool = g.serving_pool(2, 64)
+        queries = g.serving_stream(pool, 50000.0, 2000, seed=7)
+        ctx = gdist.gdist_create(0)
+        hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in pool]
+        grid = {"max_slots": [64, 128, 256], "rounds_per_step": [2, 4, 8], "expand_budget": [1 << 18, 1 << 20]}
+        t = time.time()
+        res = tune_server(ctx, hs, queries, grid)
+        res["workload"] = "serving"
+        res["seconds"] = time.time() - t
+        print(json.dumps(res["best"]), res["qps"])
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(res, f, indent=1)
+        gdist.gdist_destroy(ctx)
+        return
     if args.workload == "rings":
         w = g.rings(frames=args.frames)
         sel = np.linspace(0, 99, args.frames).astype(int)
