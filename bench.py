@@ -11,8 +11,11 @@ narrow phase, and the FP64 re-evaluation, all 100 queries in one batched
 launch.  value = queries per second over the K timed steps.  Beside it:
 p50 / p99 latency of the same frames issued one query per launch
 (gdist_query, host wall clock including launch and copy-back), the
-roofline of the dominant kernel, and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+roofline of the dominant kernel, the FP64 CPU oracle timed on a bounded
+sample of the same workload, and a serving leg: 64 resident meshes of 10K-2M
+triangles, Poisson arrivals of mixed min/max queries served by the
+continuous-batching server, against the same queries in the plain form and
+as one batched call.
 
 Prints ONE JSON line.
 """
@@ -46,6 +49,9 @@ def parse():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2411_11244_amd", "tuning", "rings_mi355x.json"),
                     help="launch options tuned for this workload ('' = library defaults)")
+    ap.add_argument("--serving-queries", type=int, default=2000,
+                    help="queries of the serving leg (0 = skip)")
+    ap.add_argument("--serving-rate", type=float, default=5000.0, help="offered queries/s of the serving leg")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed steps, run one elementwise copy reading and writing this many MiB "
                          "(the scale for rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -60,6 +66,34 @@ def traffic_record():
     if not rec or rec.get("sources_sha256") != profsum.sources_sha256():
         return None
     return rec
+
+
+def serving_leg(n_queries: int, rate: float) -> dict:
+    """The serving configuration on its own context: 64 resident meshes, a
+    seeded Poisson stream served by the tuned server, then the same queries
+    one per call and as one batch; every served result must equal its plain
+    result."""
+    import meshgen as g
+    from paper_2411_11244_amd import gdist, tune
+    from paper_2411_11244_amd.serve import compare, run_stream
+    path = os.path.join(ROOT, "paper_2411_11244_amd", "tuning", "serving_mi355x.json")
+    pool = g.serving_pool(2, 64)
+    qs = g.serving_stream(pool, rate, n_queries, seed=3)
+    ctx = gdist.gdist_create(0)
+    try:
+        tune.apply(ctx, path)
+        sc = tune.server_config(path)
+        hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in pool]
+        out = run_stream(ctx, hs, qs, sc.get("max_slots", 64), sc.get("rounds_per_step", 4), timeout_s=120)
+        cmp = compare(ctx, hs, qs, out["results"])
+    finally:
+        gdist.gdist_destroy(ctx)
+    lat = out["latency_ms"]
+    return {"workload": "64 meshes (10K-2M triangles), Poisson arrivals, half max mode, 10% overlapping",
+            "pool_tris": sum(m.n_tris for m in pool), "offered_qps": rate, "queries": n_queries,
+            "served_qps": round(n_queries / out["wall_s"], 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "server": sc, "all_ok": all(r["status"] == 0 for r in out["results"]), **cmp}
 
 
 def main():
@@ -173,6 +207,9 @@ def main():
                      for r, ref in zip(res, refs)]
             verify = {"frames": len(refs), "max_abs_err": max(errs), "pairs_match": all(pairs)}
 
+    gdist.gdist_destroy(ctx)
+    serving = serving_leg(args.serving_queries, args.serving_rate) if args.serving_queries > 0 else None
+
     out = {
         "metric": "distance queries/sec at 2x7.5M tris (1 GPU) + p50/p99 latency; HBM GB/s frac",
         "value": round(qps, 3),
@@ -199,9 +236,9 @@ def main():
         "batched_equals_plain": agree,
         "cpu_baseline": cpu,
         "verify": verify,
+        "serving": serving,
     }
     print(json.dumps(out))
-    gdist.gdist_destroy(ctx)
 
 
 if __name__ == "__main__":
