@@ -258,6 +258,31 @@ def test_conventional_bounds_same_answer(orc, gctx):
         gdist.gdist_destroy(ctx)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_fixed_depth_same_answer(orc, gctx, mode):
+    """The other ablation switch (k_cap = 1: one level per side per round, no
+    adaptive depth) changes the number of rounds, not the result; both match
+    the oracle."""
+    rng = np.random.default_rng(12)
+    A, B = g.random_mesh_of_size(rng, 6000), g.random_mesh_of_size(rng, 4000)
+    pa, pb = g.place_with_gap(rng, A, B, 0.01, g.random_rotation(rng), g.random_rotation(rng))
+    ctx = gdist.gdist_create(0)
+    try:
+        ha, hb = build(ctx, A), build(ctx, B)
+        r0 = gdist.gdist_query(ctx, ha, hb, pa, pb, mode)
+        s0 = gdist.gdist_last_stats(ctx)
+        gdist.gdist_set_option(ctx, "k_cap", 1)
+        r1 = gdist.gdist_query(ctx, ha, hb, pa, pb, mode)
+        s1 = gdist.gdist_last_stats(ctx)
+        assert r0["distance"] == r1["distance"] and r0["n_ties"] == r1["n_ties"]
+        assert (r0["tri_a"], r0["tri_b"]) == (r1["tri_a"], r1["tri_b"])
+        assert s1["rounds"] > s0["rounds"]
+        ref = oracle_query(orc, A, pa, B, pb, mode)
+        check_against_oracle(orc, r1, ref, A, pa, B, pb, mode)
+    finally:
+        gdist.gdist_destroy(ctx)
+
+
 def test_errors(gctx):
     A = g.heightfield(3, 0.0)
     bad = A.tris.copy()
