@@ -58,6 +58,9 @@ typedef enum {
 /* gdist_build flags */
 #define GDIST_BUILD_DEVICE_PTR 1u /* verts / tris are device pointers (e.g. torch
                                      tensors on the context's device)            */
+#define GDIST_BUILD_DEFORMABLE 2u /* keep the triangles' vertex indices (12 B per
+                                     triangle) so gdist_update can move the
+                                     vertices later                              */
 
 /* gdist_result_t.flags */
 #define GDIST_F_TIED 1u  /* more than one triangle pair lies within the tie
@@ -175,6 +178,20 @@ gdist_status_t gdist_set_allocator(gdist_ctx_t ctx, void* (*alloc)(size_t, void*
 gdist_status_t gdist_build(gdist_ctx_t ctx, const float* verts, uint32_t n_verts,
                            const uint32_t* tris, uint32_t n_tris, uint32_t flags,
                            gdist_mesh_t* out);
+
+/* Deformable meshes (the method covers deformable models, Sec. 1, by refitting
+ * its trees each frame, Sec. 7): give a mesh built with GDIST_BUILD_DEFORMABLE
+ * new vertex positions (same n_verts, same triangles) and refit its tree in
+ * place: every box is recomputed tight from the new triangles; the leaf
+ * order of the original build is kept (no new sort), so a large deformation
+ * may leave the tree less effective at culling but never changes a result.
+ * verts: n_verts x 3
+ * floats, host memory or (flags = GDIST_BUILD_DEVICE_PTR) device memory,
+ * copied.  E_INVALID: a mesh built without GDIST_BUILD_DEFORMABLE, n_verts
+ * other than at build time, a non-finite coordinate (the mesh is then left
+ * unchanged), unknown flags.  Synchronous. */
+gdist_status_t gdist_update(gdist_ctx_t ctx, gdist_mesh_t mesh, const float* verts, uint32_t n_verts,
+                            uint32_t flags);
 
 /* Release a mesh handle and its device memory. */
 gdist_status_t gdist_release(gdist_ctx_t ctx, gdist_mesh_t mesh);

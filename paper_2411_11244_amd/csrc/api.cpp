@@ -176,6 +176,14 @@ Mesh* find_mesh(gdist_ctx* c, gdist_mesh_t h) {
   return it == c->meshes.end() ? nullptr : it->second;
 }
 
+void free_mesh(gdist_ctx* c, Mesh* m) {
+  dfree(c, m->tris, 36ull * m->n_tris);
+  dfree(c, m->orig, 4ull * m->n_tris);
+  dfree(c, m->boxes, 48ull * m->L);
+  dfree(c, m->fl, 12ull * m->n_tris);
+  delete m;
+}
+
 uint32_t floor_log2(uint32_t x) { return 31u - (uint32_t)__builtin_clz(x); }
 
 gdist_status_t refresh_grid(gdist_ctx* c) {
@@ -521,13 +529,7 @@ gdist_status_t gdist_destroy(gdist_ctx_t c) {
   stop_async(c);
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (auto& kv : c->meshes) {
-    Mesh* m = kv.second;
-    dfree(c, m->tris, 36ull * m->n_tris);
-    dfree(c, m->orig, 4ull * m->n_tris);
-    dfree(c, m->boxes, 48ull * m->L);
-    delete m;
-  }
+  for (auto& kv : c->meshes) free_mesh(c, kv.second);
   c->meshes.clear();
   if (c->pinned) (void)hipHostFree(c->pinned);
   DevBuf* bufs[] = {&c->refit_tab, &c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->stack, &c->counts, &c->cand,
@@ -595,9 +597,11 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
   if (!verts || !tris) return fail(GDIST_E_INVALID, "NULL vertex or triangle array");
   if (nt == 0 || nt >= (1u << 31)) return fail(GDIST_E_INVALID, "n_tris = %u out of range [1, 2^31)", nt);
   if (nv == 0) return fail(GDIST_E_INVALID, "n_verts = 0");
-  if (flags & ~GDIST_BUILD_DEVICE_PTR) return fail(GDIST_E_INVALID, "unknown build flags 0x%x", flags);
+  if (flags & ~(GDIST_BUILD_DEVICE_PTR | GDIST_BUILD_DEFORMABLE))
+    return fail(GDIST_E_INVALID, "unknown build flags 0x%x", flags);
   HIPCHK(hipSetDevice(c->device));
   const bool dev = (flags & GDIST_BUILD_DEVICE_PTR) != 0;
+  const bool deformable = (flags & GDIST_BUILD_DEFORMABLE) != 0;
   gdist_status_t s = GDIST_OK;
   // temporaries
   void *dv = nullptr, *df = nullptr, *keys = nullptr, *keys2 = nullptr, *vals = nullptr, *vals2 = nullptr,
@@ -605,6 +609,7 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
   const size_t vb = 12ull * nv, fb = 12ull * nt, hb = 4ull * radix_hist_words(nt);
   Mesh* m = new Mesh();
   m->n_tris = nt;
+  m->n_verts = nv;
   m->L = 1u << floor_log2(nt);
   m->depth = floor_log2(m->L);
   auto cleanup = [&]() {
@@ -623,10 +628,7 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
   auto abort_build = [&](gdist_status_t st) {
     std::string msg = t_err;
     cleanup();
-    dfree(c, m->tris, 36ull * nt);
-    dfree(c, m->orig, 4ull * nt);
-    dfree(c, m->boxes, 48ull * m->L);
-    delete m;
+    free_mesh(c, m);
     t_err = msg;
     return st;
   };
@@ -667,12 +669,13 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
   TRY(dalloc(c, 36ull * nt, (void**)&m->tris));
   TRY(dalloc(c, 4ull * nt, (void**)&m->orig));
   TRY(dalloc(c, 48ull * m->L, (void**)&m->boxes));
+  if (deformable) TRY(dalloc(c, 12ull * nt, (void**)&m->fl));
   TRYHIP(launch_morton((const float*)dv, (const uint32_t*)df, nt, cbox, (uint64_t*)keys, (uint32_t*)vals, c->stream));
   int in_tmp = 0;
   TRYHIP(launch_radix_sort((uint64_t*)keys, (uint32_t*)vals, (uint64_t*)keys2, (uint32_t*)vals2, nt,
                            (uint32_t*)hist, c->stream, &in_tmp));
   const uint32_t* sorted = (const uint32_t*)(in_tmp ? vals2 : vals);
-  TRYHIP(launch_emit((const float*)dv, (const uint32_t*)df, nt, sorted, m->tris, m->orig, c->stream));
+  TRYHIP(launch_emit((const float*)dv, (const uint32_t*)df, nt, sorted, m->tris, m->orig, m->fl, c->stream));
   Xf32 I;
   std::memset(&I, 0, sizeof(I));
   I.R[0] = I.R[4] = I.R[8] = 1.f;
@@ -682,7 +685,7 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
 #undef TRY
 #undef TRYHIP
   cleanup();
-  m->bytes = 36ull * nt + 4ull * nt + 48ull * m->L;
+  m->bytes = 36ull * nt + 4ull * nt + 48ull * m->L + (deformable ? 12ull * nt : 0ull);
   uint64_t h = c->next_handle++;
   c->meshes[h] = m;
   *out = h;
@@ -698,12 +701,59 @@ gdist_status_t gdist_release(gdist_ctx_t c, gdist_mesh_t h) {
   if (!m) return fail(GDIST_E_HANDLE, "unknown mesh handle %llu", (unsigned long long)h);
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(hipStreamSynchronize(c->stream));
-  dfree(c, m->tris, 36ull * m->n_tris);
-  dfree(c, m->orig, 4ull * m->n_tris);
-  dfree(c, m->boxes, 48ull * m->L);
+  free_mesh(c, m);
   c->meshes.erase(h);
-  delete m;
   return GDIST_OK;
+}
+
+gdist_status_t gdist_update(gdist_ctx_t c, gdist_mesh_t h, const float* verts, uint32_t nv, uint32_t flags) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  drain_async(c);
+  Mesh* m = find_mesh(c, h);
+  if (!m) return fail(GDIST_E_HANDLE, "unknown mesh handle %llu", (unsigned long long)h);
+  if (!m->fl) return fail(GDIST_E_INVALID, "mesh %llu was not built with GDIST_BUILD_DEFORMABLE", (unsigned long long)h);
+  if (!verts) return fail(GDIST_E_INVALID, "NULL vertex array");
+  if (nv != m->n_verts) return fail(GDIST_E_INVALID, "n_verts = %u, the mesh has %u", nv, m->n_verts);
+  if (flags & ~GDIST_BUILD_DEVICE_PTR) return fail(GDIST_E_INVALID, "unknown update flags 0x%x", flags);
+  HIPCHK(hipSetDevice(c->device));
+  const size_t vb = 12ull * nv;
+  void* dv = (void*)verts;
+  void* misc = nullptr;
+  gdist_status_t s = GDIST_OK;
+  if (!(flags & GDIST_BUILD_DEVICE_PTR)) {
+    if ((s = dalloc(c, vb, &dv)) != GDIST_OK) return s;
+  }
+  if ((s = dalloc(c, 64, &misc)) == GDIST_OK) {
+    hipError_t e = hipSuccess;
+    if (!(flags & GDIST_BUILD_DEVICE_PTR)) e = hipMemcpyAsync(dv, verts, vb, hipMemcpyHostToDevice, c->stream);
+    // finiteness (and, again, the indices) before anything of the mesh changes
+    uint32_t hflags = 0;
+    uint32_t* vflags = (uint32_t*)((char*)misc + 32);
+    if (e == hipSuccess)
+      e = launch_validate_centroids((const float*)dv, nv, m->fl, m->n_tris, (int*)misc, vflags, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hflags, vflags, 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      s = fail(GDIST_E_DEVICE, "mesh update failed: %s", hipGetErrorString(e));
+    } else if (hflags & 3u) {
+      s = fail(GDIST_E_INVALID, "%s", (hflags & 2u) ? "a vertex coordinate is not finite"
+                                                    : "a triangle index is >= n_verts");
+    } else {
+      Xf32 I;
+      std::memset(&I, 0, sizeof(I));
+      I.R[0] = I.R[4] = I.R[8] = 1.f;
+      e = launch_gather_tris((const float*)dv, m->fl, m->n_tris, m->tris, c->stream);
+      if (e == hipSuccess) e = launch_refit(m->tris, m->n_tris, m->L, I, m->boxes, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(m->root, m->boxes + 6, 24, hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) s = fail(GDIST_E_DEVICE, "mesh update failed: %s", hipGetErrorString(e));
+    }
+  }
+  (void)hipStreamSynchronize(c->stream);
+  if (!(flags & GDIST_BUILD_DEVICE_PTR)) dfree(c, dv, vb);
+  dfree(c, misc, 64);
+  return s;
 }
 
 gdist_status_t gdist_mesh_info(gdist_ctx_t c, gdist_mesh_t h, gdist_mesh_info_t* out) {

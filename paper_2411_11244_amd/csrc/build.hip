@@ -272,7 +272,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
 
 // Triangles in sorted (= leaf) order, plus the caller index of each.
 __global__ void k_emit(const float* __restrict__ v, const uint32_t* __restrict__ f, uint32_t nt,
-                       const uint32_t* __restrict__ sorted, float* __restrict__ tris, uint32_t* __restrict__ orig) {
+                       const uint32_t* __restrict__ sorted, float* __restrict__ tris, uint32_t* __restrict__ orig,
+                       uint32_t* __restrict__ fl) {
   uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nt) return;
   uint32_t o = sorted[s];
@@ -280,6 +281,22 @@ __global__ void k_emit(const float* __restrict__ v, const uint32_t* __restrict__
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     uint32_t vi = f[3ull * o + c];
+    if (fl) fl[3ull * s + c] = vi;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) tris[9 * s + 3 * c + k] = v[3ull * vi + k];
+  }
+}
+
+// Deformable meshes: the triangles, in the leaf order of the original build,
+// gathered again from new vertex positions (fl holds each triangle's vertex
+// indices in that order, validated at build time).
+__global__ void k_gather_tris(const float* __restrict__ v, const uint32_t* __restrict__ fl, uint32_t nt,
+                              float* __restrict__ tris) {
+  uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nt) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    uint32_t vi = fl[3ull * s + c];
 #pragma unroll
     for (int k = 0; k < 3; ++k) tris[9 * s + 3 * c + k] = v[3ull * vi + k];
   }
@@ -331,8 +348,13 @@ hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp,
 }
 
 hipError_t launch_emit(const float* v, const uint32_t* f, uint32_t nt, const uint32_t* sorted, float* tris,
-                       uint32_t* orig, hipStream_t s) {
-  k_emit<<<(nt + 255) / 256, 256, 0, s>>>(v, f, nt, sorted, tris, orig);
+                       uint32_t* orig, uint32_t* fl, hipStream_t s) {
+  k_emit<<<(nt + 255) / 256, 256, 0, s>>>(v, f, nt, sorted, tris, orig, fl);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_tris(const float* v, const uint32_t* fl, uint32_t nt, float* tris, hipStream_t s) {
+  k_gather_tris<<<(nt + 255) / 256, 256, 0, s>>>(v, fl, nt, tris);
   return hipGetLastError();
 }
 

@@ -31,15 +31,19 @@ struct DevBuf {
 
 struct Mesh {
   uint32_t n_tris = 0, L = 0, depth = 0;
+  uint32_t n_verts = 0;
   float* tris = nullptr;
   uint32_t* orig = nullptr;
   float* boxes = nullptr;
+  uint32_t* fl = nullptr;   // deformable meshes: vertex indices of each triangle, leaf order
   float root[6] = {0, 0, 0, 0, 0, 0};
   uint64_t bytes = 0;
 };
 
 
 gdist_status_t dalloc(gdist_ctx* c, size_t bytes, void** p);
+// Free a mesh's device data and the Mesh itself.
+void free_mesh(gdist_ctx* c, Mesh* m);
 void dfree(gdist_ctx* c, void* p, size_t bytes);
 gdist_status_t ensure(gdist_ctx* c, DevBuf& b, size_t bytes);
 void release_buf(gdist_ctx* c, DevBuf& b);

@@ -144,7 +144,10 @@ size_t radix_hist_words(uint32_t n);
 hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, uint32_t n,
                              uint32_t* hist, hipStream_t s, int* result_in_tmp);
 hipError_t launch_emit(const float* v, const uint32_t* f, uint32_t nt, const uint32_t* sorted, float* tris,
-                       uint32_t* orig, hipStream_t s);
+                       uint32_t* orig, uint32_t* fl, hipStream_t s);
+// Deformable meshes: triangles (leaf order) gathered from new vertices through
+// the leaf-order index triples fl that launch_emit wrote.
+hipError_t launch_gather_tris(const float* v, const uint32_t* fl, uint32_t nt, float* tris, hipStream_t s);
 
 // refit.hip
 hipError_t launch_refit(const float* tris, uint32_t n, uint32_t L, const Xf32& T, float* boxes, hipStream_t s);

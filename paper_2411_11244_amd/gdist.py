@@ -21,6 +21,7 @@ GDIST_MIN, GDIST_MAX = 0, 1
 GDIST_OK, GDIST_E_INVALID, GDIST_E_HANDLE, GDIST_E_OOM, GDIST_E_CAPACITY, GDIST_E_DEVICE, GDIST_E_BUSY = range(7)
 STATUS_NAMES = ["OK", "E_INVALID", "E_HANDLE", "E_OOM", "E_CAPACITY", "E_DEVICE", "E_BUSY"]
 GDIST_BUILD_DEVICE_PTR = 1
+GDIST_BUILD_DEFORMABLE = 2
 GDIST_F_TIED, GDIST_F_ZERO = 1, 2
 GDIST_SERVER_DIRECT = 1
 
@@ -122,6 +123,7 @@ def lib():
         "gdist_set_option": [vp, C.c_char_p, C.c_double],
         "gdist_build": [vp, fp, u32, fp, u32, u32, C.POINTER(u64)],
         "gdist_release": [vp, u64],
+        "gdist_update": [vp, u64, fp, u32, u32],
         "gdist_mesh_info": [vp, u64, C.POINTER(gdist_mesh_info_t)],
         "gdist_mesh_export": [vp, u64, fp, fp, fp],
         "gdist_query": [vp, u64, u64, C.POINTER(gdist_pose_t), C.POINTER(gdist_pose_t), C.c_int,
@@ -155,7 +157,8 @@ def exported_symbols() -> List[str]:
             "gdist_mesh_info", "gdist_mesh_export", "gdist_query", "gdist_query_batch",
             "gdist_last_stats", "gdist_last_error", "gdist_eval_box_bounds", "gdist_eval_tri_tri",
             "gdist_server_start", "gdist_server_submit", "gdist_server_poll", "gdist_server_stats",
-            "gdist_server_stop", "gdist_query_batch_async", "gdist_sync", "gdist_set_allocator"]
+            "gdist_server_stop", "gdist_query_batch_async", "gdist_sync", "gdist_set_allocator",
+            "gdist_update"]
 
 
 def gdist_last_error() -> str:
@@ -227,6 +230,23 @@ def gdist_build(ctx: int, verts, tris, flags: int = 0) -> int:
 
 def gdist_release(ctx: int, mesh: int) -> None:
     _check(lib().gdist_release(ctx, mesh))
+
+
+def gdist_update(ctx: int, mesh: int, verts) -> None:
+    """New vertex positions (float32 [nv,3], numpy or a device tensor) for a
+    mesh built with GDIST_BUILD_DEFORMABLE; its tree is refitted in place."""
+    flags = 0
+    if _is_device(verts):
+        import torch
+        verts = verts.contiguous().to(torch.float32)
+        flags = GDIST_BUILD_DEVICE_PTR
+        nv = int(verts.shape[0])
+    else:
+        verts = np.ascontiguousarray(verts, dtype=np.float32)
+        if verts.ndim != 2 or verts.shape[1] != 3:
+            raise ValueError("verts must be [nv,3]")
+        nv = verts.shape[0]
+    _check(lib().gdist_update(ctx, mesh, _ptr(verts), nv, flags))
 
 
 def gdist_mesh_info(ctx: int, mesh: int) -> dict:
