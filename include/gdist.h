@@ -156,6 +156,12 @@ gdist_status_t gdist_destroy(gdist_ctx_t ctx);
  *   "blocks_per_cu"   persistent-kernel workgroups per compute unit
  *   "bounds"          0 = enhanced upper bounds (paper Sec. 4), 1 = conventional
  *                     bounds only (the paper's ablation)
+ *   "warm_start"      1 = temporal coherence (paper Sec. 7): the context keeps
+ *                     the pair each query reported, per (mesh a, mesh b, mode),
+ *                     and the next query of the same meshes evaluates that pair
+ *                     first to seed its bound (frame sequences); results do not
+ *                     change.  0 (default) forgets the pairs.  gdist_query and
+ *                     the batch calls use it; a server does not record pairs
  *   "memory_budget"   device bytes the context may hold (0 = unlimited)
  */
 gdist_status_t gdist_set_option(gdist_ctx_t ctx, const char* key, double value);

@@ -273,6 +273,9 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
     HIPCHK(hipEventRecord(c->ev[3], c->stream));
     HIPCHK(hipMemcpyAsync(&hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(out, p.res, sizeof(gdist_result_t) * gn, hipMemcpyDeviceToHost, c->stream));
+    if (c->warm_start)   // the reported pairs, for the next queries of the same meshes
+      HIPCHK(hipMemcpyAsync(c->warm_st.data() + g0, p.st, sizeof(SlotState) * gn, hipMemcpyDeviceToHost,
+                            c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     float kms = 0.f;
     HIPCHK(hipEventElapsedTime(&kms, c->ev[4], c->ev[5]));
@@ -374,6 +377,14 @@ gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx
     d.tA[k] = PA.t[k];
     d.tB[k] = PB.t[k];
   }
+  if (c->warm_start) {
+    auto it = c->warm.find(gdist_ctx::WarmKey{q.a, q.b, q.mode});
+    if (it != c->warm.end()) {
+      d.hint = 1u;
+      d.hint_a = it->second.first;
+      d.hint_b = it->second.second;
+    }
+  }
   double M = std::fmax(world_extent(A->root, PA), world_extent(B->root, PB));
   d.tau = 1e-12 * std::fmax(1.0, M);
   d.err_bound = 1e-13 * std::fmax(1.0, M);
@@ -441,6 +452,7 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
   // still does not fit is split in half, and later calls on this context
   // start from the smaller group size.
   std::memset(&c->last_ctl_sum, 0, sizeof(c->last_ctl_sum));
+  if (c->warm_start) c->warm_st.assign(n, SlotState{});
   uint32_t group = (c->group_hint && c->group_hint < n) ? c->group_hint : n;
   if (c->group_size && c->group_size < group) group = c->group_size;
   bool first_launch = true;
@@ -463,6 +475,12 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
       return s;
     }
     g0 += gn;
+  }
+  if (c->warm_start) {
+    // remember each query's reported pair (leaf positions) for the next query of its meshes
+    for (uint32_t i = 0; i < n; ++i)
+      if (out[i].status == GDIST_OK && c->warm_st[i].pair_a != ~0u)
+        c->warm[gdist_ctx::WarmKey{q[i].a, q[i].b, q[i].mode}] = {c->warm_st[i].pair_a, c->warm_st[i].pair_b};
   }
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
@@ -568,6 +586,11 @@ gdist_status_t gdist_set_option(gdist_ctx_t c, const char* key, double v) {
   if (k == "expand_budget") return u32opt(&c->expand_budget, 4, 1u << 30);
   if (k == "k_cap") return u32opt(&c->k_cap, 1, 8);
   if (k == "bounds") return u32opt(&c->bounds, 0, 1);
+  if (k == "warm_start") {
+    gdist_status_t st = u32opt(&c->warm_start, 0, 1);
+    if (st == GDIST_OK && !c->warm_start) c->warm.clear();
+    return st;
+  }
   if (k == "blocks_per_cu") {
     gdist_status_t s = u32opt(&c->blocks_per_cu, 0, 64);
     if (s != GDIST_OK) return s;
@@ -703,6 +726,8 @@ gdist_status_t gdist_release(gdist_ctx_t c, gdist_mesh_t h) {
   HIPCHK(hipStreamSynchronize(c->stream));
   free_mesh(c, m);
   c->meshes.erase(h);
+  for (auto it = c->warm.begin(); it != c->warm.end();)
+    it = (it->first.a == h || it->first.b == h) ? c->warm.erase(it) : std::next(it);
   return GDIST_OK;
 }
 

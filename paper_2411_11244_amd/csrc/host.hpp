@@ -82,6 +82,20 @@ struct gdist_ctx {
   bool trace = false;
   uint32_t group_hint = 0;                 // largest group of queries that fit one launch
   uint32_t group_size = 0;                 // queries per traversal launch (0 = all)
+  // warm start (option warm_start): the leaf positions of the pair reported by
+  // the latest query of each (mesh a, mesh b, mode), evaluated first by the
+  // next query of the same meshes to seed its bound
+  uint32_t warm_start = 0;
+  struct WarmKey {
+    uint64_t a, b;
+    uint32_t mode;
+    bool operator==(const WarmKey& o) const { return a == o.a && b == o.b && mode == o.mode; }
+  };
+  struct WarmHash {
+    size_t operator()(const WarmKey& k) const { return (size_t)(k.a * 0x9E3779B97F4A7C15ull ^ (k.b << 1) ^ k.mode); }
+  };
+  std::unordered_map<WarmKey, std::pair<uint32_t, uint32_t>, WarmHash> warm;
+  std::vector<gd::SlotState> warm_st;      // slot states copied back by the latest batch
   unsigned long long last_ctl_sum[gd::ST_N] = {};
   gdist_stats_t last{};
   bool busy = false;                       // a server owns the stream and workspace

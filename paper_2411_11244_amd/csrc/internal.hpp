@@ -23,6 +23,8 @@ struct SlotDesc {
   uint32_t mode;        // 0 = min, 1 = max
   uint32_t enhanced;    // 1 = enhanced bounds (Sec. 4), 0 = conventional only
   uint32_t swapped;
+  uint32_t hint;        // 1: evaluate the triangle pair (hint_a of A, hint_b of B) first
+  uint32_t hint_a, hint_b;   // leaf positions (warm start from an earlier query)
   float kappa_u;        // delta = kappa_u * M
   Xf32 T;               // B local -> A local, FP32
   double RA[9], tA[3];  // world pose of A, FP64
@@ -45,6 +47,7 @@ struct SlotState {
   uint32_t n_cand;           // candidates appended to this slot's region
   uint32_t cand_overflow;    // the region filled up
   uint32_t active;           // the slot's query is in flight (set at admission, cleared at completion)
+  uint32_t pair_a, pair_b;   // leaf positions of the reported pair (A, B roles)
 };
 
 // Candidate triangle pair for FP64 re-evaluation (positions in leaf order).

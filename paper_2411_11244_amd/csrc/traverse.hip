@@ -312,6 +312,18 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
     if (mode == 0) best = fminf(best, wave_min(dd) + delta);
     else best = fmaxf(best, fmaxf(wave_max(dd) - delta, 0.f));
   }
+  // warm start: the pair an earlier query of the same meshes reported
+  if (d.hint && d.hint_a < d.nA && d.hint_b < d.nB) {
+    float dd = mode == 0 ? __builtin_huge_valf() : 0.f;
+    if (lane == 0) {
+      V3<float> P[3], Q[3];
+      load_pair(&d, d.hint_a, d.hint_b, P, Q);
+      dd = sqrtf(mode == 0 ? tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr)
+                           : tri_tri_max_d2<float, false>(P, Q, nullptr, nullptr));
+    }
+    if (mode == 0) best = fminf(best, wave_min(dd) + delta);
+    else best = fmaxf(best, fmaxf(wave_max(dd) - delta, 0.f));
+  }
   if (lane == 0) {
     SlotState& st = p.st[s];
     st.delta = delta;
@@ -320,6 +332,8 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
     st.n_cand = 0;
     st.cand_overflow = 0;
     st.active = 1u;
+    st.pair_a = ~0u;
+    st.pair_b = ~0u;
     st.key_pair = ~0ull;
     st.best = fbits(best);
     st.best32 = mode == 0 ? fbits(__builtin_huge_valf()) : 0u;
@@ -1013,6 +1027,9 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_report(TravParams p, ui
     res.point_b[0] = qb.x; res.point_b[1] = qb.y; res.point_b[2] = qb.z;
     res.tri_a = (uint32_t)(key >> 32);
     res.tri_b = (uint32_t)(key & 0xffffffffull);
+    SlotState& sw = p.st[rr.slot];
+    sw.pair_a = cd.ia;
+    sw.pair_b = cd.ib;
   }
   if (blockIdx.x % G == 0 && threadIdx.x == 0) {
     res.n_candidates = st.n_admitted;

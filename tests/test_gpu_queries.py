@@ -343,3 +343,39 @@ def test_hard_small(orc, gctx, mode):
         gdist.gdist_release(gctx, hb)
     ref = oracle_query(orc, A, q.pose_a, B, q.pose_b, mode, "bvh")
     check_against_oracle(orc, r, ref, A, q.pose_a, B, q.pose_b, mode)
+
+
+def test_warm_start_same_answers(orc, gctx):
+    """Temporal coherence (option warm_start): each frame of a sequence seeds
+    its bound with the pair the previous frame reported.  Every result equals
+    the cold one (plain and batched), and a sample matches the oracle."""
+    A = g.torus(120, 40, 1.0, 0.1)
+    frames = [g.Query(0, 0, g.identity_pose(), g.rings_pose_b(f), m) for f in range(0, 30, 3) for m in (0, 1)]
+    cold_ctx = gdist.gdist_create(0)
+    warm_ctx = gdist.gdist_create(0)
+    try:
+        hc, hw = build(cold_ctx, A), build(warm_ctx, A)
+        gdist.gdist_set_option(warm_ctx, "warm_start", 1)
+        for i, q in enumerate(frames):
+            rc = gdist.gdist_query(cold_ctx, hc, hc, q.pose_a, q.pose_b, q.mode)
+            rw = gdist.gdist_query(warm_ctx, hw, hw, q.pose_a, q.pose_b, q.mode)
+            assert rc["distance"] == rw["distance"] and rc["n_ties"] == rw["n_ties"]
+            assert (rc["tri_a"], rc["tri_b"]) == (rw["tri_a"], rw["tri_b"])
+            assert np.array_equal(rc["point_a"], rw["point_a"])
+            if i % 7 == 0:
+                ref = oracle_query(orc, A, q.pose_a, A, q.pose_b, q.mode)
+                check_against_oracle(orc, rw, ref, A, q.pose_a, A, q.pose_b, q.mode)
+        descs_c = [gdist.make_desc(hc, hc, q.pose_a, q.pose_b, q.mode) for q in frames]
+        descs_w = [gdist.make_desc(hw, hw, q.pose_a, q.pose_b, q.mode) for q in frames]
+        bc = gdist.gdist_query_batch(cold_ctx, descs_c)
+        for _ in range(2):      # the second call starts from the first call's pairs
+            bw = gdist.gdist_query_batch(warm_ctx, descs_w)
+            for c, w in zip(bc, bw):
+                assert c["distance"] == w["distance"] and (c["tri_a"], c["tri_b"]) == (w["tri_a"], w["tri_b"])
+        gdist.gdist_release(warm_ctx, hw)      # forgets the mesh's pairs
+        hw2 = build(warm_ctx, A)
+        r = gdist.gdist_query(warm_ctx, hw2, hw2, frames[0].pose_a, frames[0].pose_b, 0)
+        assert r["distance"] == gdist.gdist_query(cold_ctx, hc, hc, frames[0].pose_a, frames[0].pose_b, 0)["distance"]
+    finally:
+        gdist.gdist_destroy(cold_ctx)
+        gdist.gdist_destroy(warm_ctx)
