@@ -326,7 +326,8 @@ void print_trace(gdist_ctx* c, uint32_t g0, uint32_t gn, const Ctl& h) {
   }
 }
 
-gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx, SlotDesc* dp, Mesh** Bout) {
+gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx, SlotDesc* dp, Mesh** Bout,
+                         bool hints) {
   Mesh* ma = find_mesh(c, q.a);
   Mesh* mb = find_mesh(c, q.b);
   if (!ma || !mb) return fail(GDIST_E_HANDLE, "query %u: unknown mesh handle", idx);
@@ -377,7 +378,7 @@ gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx
     d.tA[k] = PA.t[k];
     d.tB[k] = PB.t[k];
   }
-  if (c->warm_start) {
+  if (hints && c->warm_start) {
     auto it = c->warm.find(gdist_ctx::WarmKey{q.a, q.b, q.mode});
     if (it != c->warm.end()) {
       d.hint = 1u;
@@ -842,7 +843,7 @@ gdist_status_t gdist_query_batch_async(gdist_ctx_t c, uint32_t n, const gdist_qu
   for (uint32_t i = 0; i < n; ++i) {   // validate now: errors surface at submit
     SlotDesc d;
     Mesh* B = nullptr;
-    gdist_status_t s = make_slot(c, q[i], i, &d, &B);
+    gdist_status_t s = make_slot(c, q[i], i, &d, &B, false);
     if (s != GDIST_OK) return s;
   }
   HIPCHK(hipSetDevice(c->device));

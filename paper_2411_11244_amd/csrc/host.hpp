@@ -51,7 +51,10 @@ gdist_status_t check_pose(const gdist_pose_t* p, const char* which);
 Mesh* find_mesh(gdist_ctx* c, gdist_mesh_t h);
 // Validate one query and fill its descriptor (all but boxB); *B receives
 // the tree that the query refits.
-gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx, SlotDesc* d, Mesh** B);
+// With hints = false (validation on an API thread while a worker may run
+// queries) the warm-start pairs are not read.
+gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx, SlotDesc* d, Mesh** B,
+                         bool hints = true);
 // The batched query path (refit, grouped traversal with growing storage,
 // FP64 re-evaluation) on the context's stream and workspace.
 gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out);

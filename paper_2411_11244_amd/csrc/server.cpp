@@ -544,7 +544,7 @@ gdist_status_t gdist_server_submit(gdist_server_t sv, const gdist_query_desc_t* 
   if (!q) return fail(GDIST_E_INVALID, "NULL query");
   SlotDesc d;
   Mesh* B = nullptr;
-  gdist_status_t s = make_slot(sv->c, *q, 0, &d, &B);
+  gdist_status_t s = make_slot(sv->c, *q, 0, &d, &B, false);
   if (s != GDIST_OK) return s;
   if (B->L > sv->max_leaves)
     return fail(GDIST_E_CAPACITY, "mesh of %u triangles exceeds the server's max_tris", B->n_tris);
