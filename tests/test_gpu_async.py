@@ -120,3 +120,26 @@ def test_caller_allocator(gctx):
         gdist.gdist_destroy(ctx)
     assert not live and counts["free"] == counts["alloc"]
     del keep
+
+
+def test_async_with_warm_start(gctx):
+    """Asynchronous batches on a context with warm_start: the worker records
+    the reported pairs while the caller submits the next batch; every result
+    equals the synchronous cold one."""
+    hs, descs = _workload(gctx, 31, 30)
+    try:
+        want = gdist.gdist_query_batch(gctx, descs)
+    finally:
+        for h in hs:
+            gdist.gdist_release(gctx, h)
+    ctx = gdist.gdist_create(0)
+    try:
+        gdist.gdist_set_option(ctx, "warm_start", 1)
+        hs2, descs2 = _workload(ctx, 31, 30)
+        pend = [gdist.gdist_query_batch_async(ctx, descs2) for _ in range(4)]
+        gdist.gdist_sync(ctx)
+        for b in pend:
+            for r, a in zip(b.results(), want):
+                _same(r, a)
+    finally:
+        gdist.gdist_destroy(ctx)
