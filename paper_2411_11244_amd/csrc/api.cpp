@@ -271,12 +271,17 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
     HIPCHK(hipEventRecord(c->ev[5], c->stream));
     HIPCHK(launch_reeval(p, c->stream));
     HIPCHK(hipEventRecord(c->ev[3], c->stream));
-    HIPCHK(hipMemcpyAsync(&hctl, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(out, p.res, sizeof(gdist_result_t) * gn, hipMemcpyDeviceToHost, c->stream));
+    // copy-back through pinned staging, one stream synchronisation
+    char* back = (char*)c->pinned + c->back_off;
+    HIPCHK(hipMemcpyAsync(back, c->ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(back + c->back_res, p.res, sizeof(gdist_result_t) * gn, hipMemcpyDeviceToHost,
+                          c->stream));
     if (c->warm_start)   // the reported pairs, for the next queries of the same meshes
-      HIPCHK(hipMemcpyAsync(c->warm_st.data() + g0, p.st, sizeof(SlotState) * gn, hipMemcpyDeviceToHost,
-                            c->stream));
+      HIPCHK(hipMemcpyAsync(back + c->back_st, p.st, sizeof(SlotState) * gn, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    std::memcpy(&hctl, back, sizeof(Ctl));
+    std::memcpy(out, back + c->back_res, sizeof(gdist_result_t) * gn);
+    if (c->warm_start) std::memcpy(c->warm_st.data() + g0, back + c->back_st, sizeof(SlotState) * gn);
     float kms = 0.f;
     HIPCHK(hipEventElapsedTime(&kms, c->ev[4], c->ev[5]));
     c->last.ms_traverse_kernel += kms;
@@ -433,7 +438,12 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
   }
   const size_t desc_bytes = (sizeof(SlotDesc) * n + 255) & ~(size_t)255;
   const size_t tab_cap = sizeof(RefitJob) * n + sizeof(ReduceJob) * n * kMaxRefitPasses + 256;
-  if ((s = ensure_pinned(c, desc_bytes + tab_cap)) != GDIST_OK) return s;
+  // copy-back area after the tables: control block, results, slot states
+  const auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  c->back_off = al(desc_bytes + tab_cap);
+  c->back_res = al(sizeof(Ctl));
+  c->back_st = c->back_res + al(sizeof(gdist_result_t) * n);
+  if ((s = ensure_pinned(c, c->back_off + c->back_st + sizeof(SlotState) * n)) != GDIST_OK) return s;
   std::memcpy(c->pinned, desc.data(), sizeof(SlotDesc) * n);
   RefitPlan rplan;
   const size_t tab_bytes = plan_refit_batch(jobs.data(), n, (char*)c->pinned + desc_bytes, tab_cap, &rplan);

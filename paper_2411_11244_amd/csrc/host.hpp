@@ -78,8 +78,9 @@ struct gdist_ctx {
   uint64_t memory_budget = 0, bytes_held = 0;
   // workspace
   DevBuf ws_boxes, front[2], leaf[2], stack, counts, cand, cand64, ctl, desc, st, res, refit_tab;
-  void* pinned = nullptr;       // host staging for descriptors and job tables
+  void* pinned = nullptr;       // host staging: descriptors and job tables, then the copy-back area
   size_t pinned_bytes = 0;
+  size_t back_off = 0, back_res = 0, back_st = 0;   // copy-back area: Ctl, results, slot states
   uint32_t trav_blocks = 0, trav_threads = 0;
   int wall_khz = 0;
   bool trace = false;
