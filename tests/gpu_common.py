@@ -13,8 +13,10 @@ def on_triangle(x, T, tol):
     a, b, c = T
     n = np.cross(b - a, c - a)
     nn = n @ n
-    if nn == 0:
-        # degenerate: distance to its three edges
+    size = max(np.linalg.norm(b - a), np.linalg.norm(c - a), np.linalg.norm(c - b))
+    if nn <= (1e-10 * size * size) ** 2:
+        # (numerically) degenerate, e.g. collinear vertices after a rotation:
+        # distance to its three edges
         def segd(p, u, v):
             d = v - u
             L = d @ d

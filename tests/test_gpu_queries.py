@@ -379,3 +379,38 @@ def test_warm_start_same_answers(orc, gctx):
     finally:
         gdist.gdist_destroy(cold_ctx)
         gdist.gdist_destroy(warm_ctx)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_degenerate_triangles(orc, gctx, mode):
+    """Zero-area triangles are accepted: a soup where a third of the
+    triangles collapse to a point, a segment (repeated vertex) or a line
+    (collinear vertices), against a heightfield, in both modes; the FP64
+    brute-force oracle decides."""
+    rng = np.random.default_rng(23)
+    A = g.random_soup(rng, 600, 0.6, 0.08)
+    v = A.verts.copy()
+    t = A.tris.astype(np.int64)
+    for i in range(0, len(t), 3):
+        k = (i // 3) % 3
+        a, b, c = t[i]
+        if k == 0:
+            v[b] = v[a]; v[c] = v[a]                      # a point
+        elif k == 1:
+            t[i, 2] = a                                    # a segment through a repeated index
+        else:                                              # exactly collinear (dyadic coordinates)
+            base = np.round(v[a] * 1024.0) / 1024.0
+            step = np.array([1.0, 2.0, -1.0], np.float32) / 256.0
+            v[a], v[b], v[c] = base, base + step, base + 3.0 * step
+    A = g.Mesh(v, t.astype(np.uint32))
+    B = g.heightfield(24, 0.05, rng)
+    ha, hb = build(gctx, A), build(gctx, B)
+    try:
+        for gap in (0.02, -0.1):
+            pa, pb = g.place_with_gap(rng, A, B, gap, g.random_rotation(rng), g.random_rotation(rng))
+            r = gdist.gdist_query(gctx, ha, hb, pa, pb, mode)
+            ref = oracle_query(orc, A, pa, B, pb, mode, "brute")
+            check_against_oracle(orc, r, ref, A, pa, B, pb, mode)
+    finally:
+        gdist.gdist_release(gctx, ha)
+        gdist.gdist_release(gctx, hb)
