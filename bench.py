@@ -208,7 +208,12 @@ def main():
             verify = {"frames": len(refs), "max_abs_err": max(errs), "pairs_match": all(pairs)}
 
     gdist.gdist_destroy(ctx)
-    serving = serving_leg(args.serving_queries, args.serving_rate) if args.serving_queries > 0 else None
+    serving = None
+    if args.serving_queries > 0:
+        try:
+            serving = serving_leg(args.serving_queries, args.serving_rate)
+        except Exception as e:   # the headline line is printed regardless
+            serving = {"error": f"{type(e).__name__}: {e}"}
 
     out = {
         "metric": "distance queries/sec at 2x7.5M tris (1 GPU) + p50/p99 latency; HBM GB/s frac",
