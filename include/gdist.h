@@ -150,8 +150,9 @@ gdist_status_t gdist_destroy(gdist_ctx_t ctx);
  *   "max_retries"     capacity doublings before GDIST_E_CAPACITY
  *   "group_size"      queries of a batch traversed together per launch (0 = all);
  *                     smaller groups keep their trees' boxes in the caches
- *   "expand_budget"   C of the adaptive depth rule (largest k with 4^k n < C)
- *   "k_cap"           largest expansion depth per side and round (1..8)
+ *   "expand_budget"   C of the adaptive depth rule (largest k with 4^k n < C;
+ *                     default 2^22)
+ *   "k_cap"           largest expansion depth per side and round (1..8, default 8)
  *   "kappa"           FP32 inflation: delta = kappa * 2^-24 * M
  *   "blocks_per_cu"   persistent-kernel workgroups per compute unit
  *   "bounds"          0 = enhanced upper bounds (paper Sec. 4), 1 = conventional

@@ -28,7 +28,7 @@ from . import gdist, tune
 HERE = os.path.dirname(os.path.abspath(__file__))
 VARIANTS = (("gdist", {}), ("v1", {"bounds": 1}), ("v2", {"k_cap": 1}))
 NODES = ("child_pairs", "entries_pushed", "leaf_pairs")
-DEFAULT_K_CAP = 5   # the library's default
+DEFAULT_K_CAP = 8   # the library's default
 
 
 def _workload(name: str, ctx: int) -> Tuple[List, List[int]]:

@@ -73,7 +73,7 @@ struct gdist_ctx {
   // tunables
   uint32_t front_cap = 1u << 26, leaf_cap = 1u << 26, cand_cap = 1u << 21;
   uint64_t stack_cap = 1ull << 27;
-  uint32_t max_retries = 8, expand_budget = 1u << 18, k_cap = 5, blocks_per_cu = 0, bounds = 0;
+  uint32_t max_retries = 8, expand_budget = 1u << 22, k_cap = 8, blocks_per_cu = 0, bounds = 0;
   double kappa = 64.0;
   uint64_t memory_budget = 0, bytes_held = 0;
   // workspace

@@ -93,7 +93,7 @@ def test_server_storage_growth(gctx, served):
         out = run_stream(gctx, handles, qs[:24], max_slots=16, rounds_per_step=2, front_capacity=64,
                          time_scale=0.0, timeout_s=120, stack_capacity=256)
     finally:
-        gdist.gdist_set_option(gctx, "expand_budget", 1 << 18)
+        gdist.gdist_set_option(gctx, "expand_budget", 1 << 22)
     for r, a in zip(out["results"], alone[:24]):
         _same(r, a)
     assert out["stats"]["requeued"] > 0
