@@ -271,7 +271,9 @@ typedef struct gdist_server* gdist_server_t;
 
 typedef struct {
   uint32_t max_slots;       /* queries in flight, 1..512 (0 = 64)                        */
-  uint32_t rounds_per_step; /* traversal rounds per device step (0 = 4)                  */
+  uint32_t rounds_per_step; /* traversal rounds per device step while queries wait to be
+                               admitted (0 = 4); with none waiting a step runs up to 64
+                               rounds, so a lone query usually completes in one step      */
   uint64_t front_capacity;  /* entries per front and per leaf-pair buffer (0 = 2^25, at
                                most 2^28); a step's rounds expand at most about a
                                quarter of it, the surplus waits on the spill stack       */

@@ -72,7 +72,7 @@ struct gdist_server {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
-  hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};   // short steps, long steps
   TravParams gp{};            // the step parameters the graph (or the direct mode) was set up for
   bool gp_set = false;
   uint32_t graph_mode = 0;
@@ -208,9 +208,22 @@ hipError_t enqueue_step(gdist_server* sv, const TravParams& p) {
 }
 
 void drop_graph(gdist_server* sv) {
-  if (sv->gexec) (void)hipGraphExecDestroy(sv->gexec);
-  sv->gexec = nullptr;
+  for (hipGraphExec_t& g : sv->gexec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
   sv->graph_mode = 0;
+}
+
+// A step runs at most rounds_per_step rounds while queries wait to be
+// admitted; with nobody waiting it runs up to kLongRounds, so a lone query
+// usually completes within one step (the launch still ends as soon as every
+// traversal has drained).
+constexpr uint32_t kLongRounds = 64;
+TravParams step_params(const TravParams& p, bool lng) {
+  TravParams q = p;
+  if (lng && q.max_rounds < kLongRounds) q.max_rounds = kLongRounds;
+  return q;
 }
 
 // Build the step graph for parameters p: a cooperative kernel node for the
@@ -223,28 +236,32 @@ void build_graph(gdist_server* sv, const TravParams& p) {
   sv->gp = p;
   sv->gp_set = true;
   if (sv->cfg.flags & GDIST_SERVER_DIRECT) return;
-  hipGraph_t g = nullptr, tail = nullptr;
-  hipGraphNode_t tn = nullptr, cn = nullptr;
-  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
-  if (e == hipSuccess) {
-    hipError_t e1 = enqueue_tail(sv, p);
-    hipError_t e2 = hipStreamEndCapture(c->stream, &tail);
-    e = e1 != hipSuccess ? e1 : e2;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    const TravParams q = step_params(p, i == 1);
+    hipGraph_t g = nullptr, tail = nullptr;
+    hipGraphNode_t tn = nullptr, cn = nullptr;
+    e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t e1 = enqueue_tail(sv, q);
+      hipError_t e2 = hipStreamEndCapture(c->stream, &tail);
+      e = e1 != hipSuccess ? e1 : e2;
+    }
+    size_t n_tail = 0;
+    if (e == hipSuccess) e = hipGraphGetNodes(tail, nullptr, &n_tail);
+    if (e == hipSuccess && n_tail != 7) e = hipErrorInvalidValue;
+    if (e == hipSuccess) e = hipGraphCreate(&g, 0);
+    if (e == hipSuccess) e = add_traverse_node(g, q, c->trav_blocks, c->trav_threads, &tn);
+    if (e == hipSuccess) e = hipGraphAddChildGraphNode(&cn, g, &tn, 1, tail);
+    if (e == hipSuccess) e = hipGraphInstantiate(&sv->gexec[i], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (tail) (void)hipGraphDestroy(tail);
   }
-  size_t n_tail = 0;
-  if (e == hipSuccess) e = hipGraphGetNodes(tail, nullptr, &n_tail);
-  if (e == hipSuccess && n_tail != 7) e = hipErrorInvalidValue;
-  if (e == hipSuccess) e = hipGraphCreate(&g, 0);
-  if (e == hipSuccess) e = add_traverse_node(g, p, c->trav_blocks, c->trav_threads, &tn);
-  if (e == hipSuccess) e = hipGraphAddChildGraphNode(&cn, g, &tn, 1, tail);
-  if (e == hipSuccess) e = hipGraphInstantiate(&sv->gexec, g, nullptr, nullptr, 0);
-  if (g) (void)hipGraphDestroy(g);
-  if (tail) (void)hipGraphDestroy(tail);
   if (e == hipSuccess) {
     sv->graph_mode = 1;
   } else {
     (void)hipGetLastError();
-    sv->gexec = nullptr;
+    drop_graph(sv);
   }
 }
 
@@ -326,9 +343,14 @@ gdist_status_t step(gdist_server* sv) {
   }
   if (sv->n_active == 0) return GDIST_OK;
   // 2-5. traversal, live counts, completion, re-evaluation, report copy
+  bool lng;
+  {
+    std::lock_guard<std::mutex> g(sv->mu);
+    lng = sv->pending.empty();
+  }
   HIPCHK(hipEventRecord(sv->ev[0], c->stream));
-  if (sv->gexec) HIPCHK(hipGraphLaunch(sv->gexec, c->stream));
-  else HIPCHK(enqueue_step(sv, p));
+  if (sv->gexec[lng]) HIPCHK(hipGraphLaunch(sv->gexec[lng], c->stream));
+  else HIPCHK(enqueue_step(sv, step_params(p, lng)));
   HIPCHK(hipEventRecord(sv->ev[1], c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   float ms = 0.f;
@@ -344,7 +366,7 @@ gdist_status_t step(gdist_server* sv) {
     sv->stats.steps++;
     sv->stats.rounds += head.rounds_done;
     sv->stats.device_ms += ms;
-    if (sv->gexec) sv->stats.graph_steps++;
+    if (sv->gexec[lng]) sv->stats.graph_steps++;
   }
   if (head.abort) return fail(GDIST_E_DEVICE, "server step: grid barrier timed out");
   if (head.overflow) {
