@@ -200,7 +200,10 @@ gdist_status_t gdist_build(gdist_ctx_t ctx, const float* verts, uint32_t n_verts
 gdist_status_t gdist_update(gdist_ctx_t ctx, gdist_mesh_t mesh, const float* verts, uint32_t n_verts,
                             uint32_t flags);
 
-/* Release a mesh handle and its device memory. */
+/* Release a mesh handle and its device memory.  Queued asynchronous batches
+ * of the context complete first, so a handle still in flight is released
+ * after the work that uses it; the warm-start pairs of the mesh are dropped.
+ * E_BUSY while a server runs on the context. */
 gdist_status_t gdist_release(gdist_ctx_t ctx, gdist_mesh_t mesh);
 
 gdist_status_t gdist_mesh_info(gdist_ctx_t ctx, gdist_mesh_t mesh, gdist_mesh_info_t* out);
