@@ -1105,8 +1105,11 @@ __global__ void k_step_select(TravParams p, const StepHead* __restrict__ head, c
   }
 }
 
+// Workgroups per listed slot in the re-evaluation: about 4,096 workgroups in
+// all (a slot may hold 10^5 candidates; slots with few exit at once), at most
+// 64 per slot.
 uint32_t reeval_groups(uint32_t n_list) {
-  uint32_t g = 1024u / (n_list ? n_list : 1u);
+  uint32_t g = 4096u / (n_list ? n_list : 1u);
   return g < 1u ? 1u : (g > 64u ? 64u : g);
 }
 
