@@ -165,8 +165,8 @@ def main():
     ctx = gdist.gdist_create(0)
     hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in w.meshes]
     descs = [gdist.make_desc(hs[q.a], hs[q.b], q.pose_a, q.pose_b, q.mode) for q in w.queries]
-    grid = {"expand_budget": [1 << 20, 1 << 22], "k_cap": [5, 7], "blocks_per_cu": [0],
-            "front_capacity": [1 << 27], "group_size": [16, 12, 10, 8]}
+    grid = {"expand_budget": [1 << 20, 1 << 22], "k_cap": [7, 8], "blocks_per_cu": [0],
+            "front_capacity": [1 << 27], "group_size": [24, 20, 16, 12]}
     t = time.time()
     res = tune(ctx, descs, grid, args.reps)
     res["workload"] = args.workload
