@@ -230,6 +230,14 @@ gdist_status_t gdist_query(gdist_ctx_t ctx, gdist_mesh_t a, gdist_mesh_t b,
  * returns for it alone.  out[i].status carries the per-query status (a query
  * that could not complete, e.g. after E_CAPACITY, holds that status and a NaN
  * distance); the call returns the first non-OK status, or OK.  Synchronous. */
+/* One mesh against n others (the paper's future work, Sec. 8): mesh a at
+ * pose pa against b[i] at pose pb[i], all in one batched call, result i in
+ * out[i] (same per-query statuses and return value as gdist_query_batch).
+ * b, pb and out hold n entries each, caller-owned.  Synchronous. */
+gdist_status_t gdist_query_one_to_many(gdist_ctx_t ctx, gdist_mesh_t a, const gdist_pose_t* pa, uint32_t n,
+                                       const gdist_mesh_t* b, const gdist_pose_t* pb, gdist_mode_t mode,
+                                       gdist_result_t* out);
+
 gdist_status_t gdist_query_batch(gdist_ctx_t ctx, uint32_t n, const gdist_query_desc_t* q,
                                  gdist_result_t* out);
 

@@ -844,6 +844,27 @@ gdist_status_t gdist_query_batch(gdist_ctx_t c, uint32_t n, const gdist_query_de
   return run_queries(c, n, q, out);
 }
 
+gdist_status_t gdist_query_one_to_many(gdist_ctx_t c, gdist_mesh_t a, const gdist_pose_t* pa, uint32_t n,
+                                       const gdist_mesh_t* b, const gdist_pose_t* pb, gdist_mode_t mode,
+                                       gdist_result_t* out) {
+  if (!c) return fail(GDIST_E_HANDLE, "NULL context");
+  if (c->busy) return fail(GDIST_E_BUSY, "a server runs on this context");
+  if (n == 0) return GDIST_OK;
+  if (!pa || !b || !pb || !out) return fail(GDIST_E_INVALID, "NULL pose, handle or result array");
+  std::vector<gdist_query_desc_t> q(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    std::memset(&q[i], 0, sizeof(q[i]));
+    q[i].a = a;
+    q[i].b = b[i];
+    q[i].pa = *pa;
+    q[i].pb = pb[i];
+    q[i].mode = (uint32_t)mode;
+  }
+  drain_async(c);
+  HIPCHK(hipSetDevice(c->device));
+  return run_queries(c, n, q.data(), out);
+}
+
 gdist_status_t gdist_query_batch_async(gdist_ctx_t c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out,
                                        void* hip_stream) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");

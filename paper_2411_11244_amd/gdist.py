@@ -129,6 +129,8 @@ def lib():
         "gdist_query": [vp, u64, u64, C.POINTER(gdist_pose_t), C.POINTER(gdist_pose_t), C.c_int,
                         C.POINTER(gdist_result_t)],
         "gdist_query_batch": [vp, u32, C.POINTER(gdist_query_desc_t), C.POINTER(gdist_result_t)],
+        "gdist_query_one_to_many": [vp, u64, C.POINTER(gdist_pose_t), u32, C.POINTER(u64), C.POINTER(gdist_pose_t),
+                                    C.c_int, C.POINTER(gdist_result_t)],
         "gdist_last_stats": [vp, C.POINTER(gdist_stats_t)],
         "gdist_eval_box_bounds": [vp, u32, fp, fp, fp],
         "gdist_eval_tri_tri": [vp, u32, fp, fp, u32, fp, dp],
@@ -158,7 +160,7 @@ def exported_symbols() -> List[str]:
             "gdist_last_stats", "gdist_last_error", "gdist_eval_box_bounds", "gdist_eval_tri_tri",
             "gdist_server_start", "gdist_server_submit", "gdist_server_poll", "gdist_server_stats",
             "gdist_server_stop", "gdist_query_batch_async", "gdist_sync", "gdist_set_allocator",
-            "gdist_update"]
+            "gdist_update", "gdist_query_one_to_many"]
 
 
 def gdist_last_error() -> str:
@@ -291,6 +293,20 @@ def gdist_query_batch(ctx: int, descs: Sequence[gdist_query_desc_t], check: bool
     arr = (gdist_query_desc_t * n)(*descs)
     res = (gdist_result_t * n)()
     st = lib().gdist_query_batch(ctx, n, arr, res)
+    if check:
+        _check(st)
+    return [res[i].as_dict() for i in range(n)]
+
+
+def gdist_query_one_to_many(ctx: int, a: int, pose_a, bs: Sequence[int], poses_b, mode: int,
+                            check: bool = True) -> List[dict]:
+    """Mesh a at pose_a against bs[i] at poses_b[i] ((R, t) pairs), one batched call."""
+    n = len(bs)
+    hb = (C.c_uint64 * n)(*[int(h) for h in bs])
+    pb = (gdist_pose_t * n)(*[make_pose(*p) for p in poses_b])
+    res = (gdist_result_t * n)()
+    pa = make_pose(*pose_a)
+    st = lib().gdist_query_one_to_many(ctx, a, C.byref(pa), n, hb, pb, int(mode), res)
     if check:
         _check(st)
     return [res[i].as_dict() for i in range(n)]

@@ -414,3 +414,32 @@ def test_degenerate_triangles(orc, gctx, mode):
     finally:
         gdist.gdist_release(gctx, ha)
         gdist.gdist_release(gctx, hb)
+
+
+def test_one_to_many_equals_single(orc, gctx):
+    """One mesh against N meshes and poses in one call (gdist_query_one_to_many)
+    equals the N queries one by one; a sample matches the oracle."""
+    rng = np.random.default_rng(61)
+    A = g.random_mesh_of_size(rng, 3000)
+    others = [g.random_mesh_of_size(rng, t) for t in (200, 5000, 900, 12000, 40)]
+    ha = build(gctx, A)
+    hbs = [build(gctx, m) for m in others]
+    try:
+        pa = (g.random_rotation(rng), np.zeros(3))
+        for mode in (0, 1):
+            bs, poses, ms = [], [], []
+            for i in range(12):
+                j = i % len(others)
+                _, pb = g.place_with_gap(rng, A, others[j], [0.01, 0.3, -0.05][i % 3], pa[0], g.random_rotation(rng))
+                bs.append(hbs[j]); poses.append(pb); ms.append(others[j])
+            res = gdist.gdist_query_one_to_many(gctx, ha, pa, bs, poses, mode)
+            for i, (r, hb, pb) in enumerate(zip(res, bs, poses)):
+                s = gdist.gdist_query(gctx, ha, hb, pa, pb, mode)
+                assert r["distance"] == s["distance"] and (r["tri_a"], r["tri_b"]) == (s["tri_a"], s["tri_b"])
+                if i % 5 == 0:
+                    ref = oracle_query(orc, A, pa, ms[i], pb, mode)
+                    check_against_oracle(orc, r, ref, A, pa, ms[i], pb, mode)
+    finally:
+        gdist.gdist_release(gctx, ha)
+        for h in hbs:
+            gdist.gdist_release(gctx, h)
