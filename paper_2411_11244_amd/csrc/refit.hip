@@ -15,7 +15,7 @@
 
 namespace gd {
 
-constexpr int kRefitThreads = 256;
+constexpr int kRefitThreads = 512;
 
 __global__ __launch_bounds__(kRefitThreads) void k_refit_leaves(const float* __restrict__ tris, uint32_t n,
                                                                  uint32_t L, Xf32 T, float* __restrict__ boxes,
