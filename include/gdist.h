@@ -108,7 +108,13 @@ typedef struct {
 
 /* Counters of the most recent gdist_query / gdist_query_batch call on a
  * context, summed over its queries.  Byte counts are algorithmic (what the
- * method must move), not hardware counters. */
+ * method must move, counted in the kernels), not hardware counters:
+ *   bytes_traversal = 16 per entry popped + 24 per child box read (2^kA + 2^kB
+ *                     per popped entry expanded kA levels in A, kB in B; each
+ *                     sibling box once) + 16 per entry pushed;
+ *   bytes_narrow    = 16 per leaf pair + 36 per triangle read (tA + tB per leaf
+ *                     pair of leaves holding tA and tB triangles);
+ *   bytes_reeval    = 144 per candidate (its two triangles). */
 typedef struct {
   uint64_t rounds;          /* expansion rounds (grid-wide steps)                  */
   uint64_t entries_popped;  /* front entries expanded                              */
@@ -121,13 +127,16 @@ typedef struct {
   uint64_t front_peak;      /* largest front (entries)                             */
   uint64_t bytes_refit;     /* refit: triangles read + boxes written               */
   uint64_t bytes_traversal; /* entries read + child boxes read + entries written   */
-  uint64_t bytes_narrow;    /* leaf pairs read + triangles read + candidates       */
+  uint64_t bytes_narrow;    /* leaf pairs read + their triangles read              */
   uint64_t retries;         /* capacity retries                                    */
   double ms_refit;          /* device time of the refit kernels (HIP events)       */
   double ms_traversal;      /* device time of the traversal + re-eval kernel       */
   double ms_total;          /* device time of the whole query (refit to result)    */
   double ms_traverse_kernel;/* summed device time of the k_traverse launches alone   */
   uint64_t traverse_launches;/* k_traverse launches (groups and capacity retries)     */
+  uint64_t child_boxes;     /* child boxes read: sum of 2^kA + 2^kB over popped entries */
+  uint64_t leaf_tris;       /* triangles read: sum of tA + tB over leaf pairs          */
+  uint64_t bytes_reeval;    /* FP64 re-evaluation: 144 per candidate                   */
 } gdist_stats_t;
 
 /* ---------------------------------------------------------------- context */

@@ -310,6 +310,7 @@ class Query:
     pose_b: Pose
     mode: int = 0          # 0 = min distance, 1 = max distance
     arrival: float = 0.0   # seconds (serving streams only)
+    gap: float = float("nan")   # support-function gap of the placement (< 0: overlapping), where drawn
 
 
 @dataclass
@@ -421,7 +422,7 @@ def serving_stream(pool: List[Mesh], rate: float, n_queries: int, seed: int = 3,
             g = math.exp(rng.uniform(math.log(1e-3), math.log(1.0)))
         pa, pb = place_with_gap(rng, pool[a], pool[b], g, ra, rb)
         mode = 1 if rng.uniform() < max_frac else 0
-        qs.append(Query(a, b, pa, pb, mode, t))
+        qs.append(Query(a, b, pa, pb, mode, t, g))
     return qs
 
 

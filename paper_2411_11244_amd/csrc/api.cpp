@@ -391,6 +391,20 @@ gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx
       d.hint_b = it->second.second;
     }
   }
+  // The FP32 transform of B's vertices into A's frame rounds R, t and three
+  // fused multiply-adds per coordinate; its error grows with |x_B| (B's local
+  // coordinates, up to sqrt(3) max|B root| after the rotation) and |t|, which
+  // can far exceed the query frame's coordinates when they cancel.  M for the
+  // error window is at least that.
+  {
+    double ma = 0.0, mb = 0.0, mt = 0.0;
+    for (int k = 0; k < 6; ++k) {
+      ma = std::fmax(ma, std::fabs((double)A->root[k]));
+      mb = std::fmax(mb, std::fabs((double)B->root[k]));
+    }
+    for (int k = 0; k < 3; ++k) mt = std::fmax(mt, std::fabs((double)d.T.t[k]));
+    d.m_floor = (float)std::fmax(ma, std::sqrt(3.0) * mb + mt);
+  }
   double M = std::fmax(world_extent(A->root, PA), world_extent(B->root, PB));
   d.tau = 1e-12 * std::fmax(1.0, M);
   d.err_bound = 1e-13 * std::fmax(1.0, M);
@@ -403,7 +417,29 @@ struct SlotPlan {
   size_t box_off;  // float offset of B's refitted boxes in ws_boxes
 };
 
+// The query workspace is a cache that grows on demand.  When a query call
+// runs out of device memory (the budget or the device), the whole cache is
+// released, so the context holds only its meshes again and stays usable.
+void release_workspace(gdist_ctx* c) {
+  (void)hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->refit_tab, &c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->stack,
+                    &c->counts, &c->cand, &c->cand64, &c->ctl, &c->desc, &c->st, &c->res};
+  for (DevBuf* b : bufs) release_buf(c, *b);
+}
+
+gdist_status_t run_queries_impl(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out);
+
 gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out) {
+  gdist_status_t s = run_queries_impl(c, n, q, out);
+  if (s == GDIST_E_OOM) {
+    std::string msg = t_err;
+    release_workspace(c);
+    t_err = msg;
+  }
+  return s;
+}
+
+gdist_status_t run_queries_impl(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out) {
   if (n == 0) return GDIST_OK;
   if (!q || !out) return fail(GDIST_E_INVALID, "NULL query or result array");
   std::vector<SlotDesc> desc(n);
@@ -510,8 +546,14 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
   c->last.tri_full = st[ST_FULL];
   c->last.candidates = st[ST_CAND];
   c->last.front_peak = st[ST_PEAK];
-  c->last.bytes_traversal = 16ull * c->last.entries_popped + 48ull * c->last.child_pairs + 16ull * c->last.entries_pushed;
-  c->last.bytes_narrow = 16ull * c->last.leaf_pairs + 72ull * c->last.tri_pairs + 16ull * c->last.candidates;
+  c->last.child_boxes = st[ST_BOXES];
+  c->last.leaf_tris = st[ST_LTRI];
+  // algorithmic bytes: entries popped, child boxes (siblings read once per
+  // popped entry) and entries pushed; leaf-pair entries and their triangles;
+  // FP64 re-evaluation of the candidates (two triangles, 72 B each read twice)
+  c->last.bytes_traversal = 16ull * c->last.entries_popped + 24ull * c->last.child_boxes + 16ull * c->last.entries_pushed;
+  c->last.bytes_narrow = 16ull * c->last.leaf_pairs + 36ull * c->last.leaf_tris;
+  c->last.bytes_reeval = 144ull * c->last.candidates;
   gdist_status_t first = GDIST_OK;
   for (uint32_t i = 0; i < n; ++i)
     if (out[i].status != GDIST_OK && first == GDIST_OK) first = (gdist_status_t)out[i].status;
@@ -561,9 +603,7 @@ gdist_status_t gdist_destroy(gdist_ctx_t c) {
   for (auto& kv : c->meshes) free_mesh(c, kv.second);
   c->meshes.clear();
   if (c->pinned) (void)hipHostFree(c->pinned);
-  DevBuf* bufs[] = {&c->refit_tab, &c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->stack, &c->counts, &c->cand,
-                    &c->cand64, &c->ctl, &c->desc, &c->st, &c->res};
-  for (DevBuf* b : bufs) release_buf(c, *b);
+  release_workspace(c);
   for (int i = 0; i < 6; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->stream) (void)hipStreamDestroy(c->stream);

@@ -26,6 +26,8 @@ struct SlotDesc {
   uint32_t hint;        // 1: evaluate the triangle pair (hint_a of A, hint_b of B) first
   uint32_t hint_a, hint_b;   // leaf positions (warm start from an earlier query)
   float kappa_u;        // delta = kappa_u * M
+  float m_floor;        // least M: bounds the FP32 transform's rounding, which grows with
+                        //   B's local coordinates and the translation, not with the query frame
   Xf32 T;               // B local -> A local, FP32
   double RA[9], tA[3];  // world pose of A, FP64
   double RB[9], tB[3];  // world pose of B, FP64
@@ -57,9 +59,11 @@ struct Cand {
   uint32_t ia, ib;
 };
 
+// ST_BOXES: child boxes read by the expansion, 2^kA + 2^kB per popped entry;
+// ST_LTRI: triangles read by the narrow phase, tA + tB per leaf pair.
 enum StatIdx {
   ST_POPPED = 0, ST_CHILD = 1, ST_PUSHED = 2, ST_LEAF = 3, ST_TRI = 4, ST_CAND = 5, ST_PEAK = 6, ST_ROUNDS = 7,
-  ST_FULL = 8, ST_N = 9
+  ST_FULL = 8, ST_BOXES = 9, ST_LTRI = 10, ST_N = 11
 };
 
 constexpr uint32_t kTraceRounds = 48;

@@ -153,6 +153,11 @@ struct WaveStats {
 __device__ __forceinline__ void add_stat(WaveStats& ws, int idx, bool pred) {
   ws.v[idx] += (uint32_t)__popcll(__ballot(pred));
 }
+// Per-lane byte-count operands (summed over the wave once per round): child
+// boxes read per popped entry and triangles read per leaf pair.
+struct LaneStats {
+  uint32_t boxes, ltris;
+};
 
 __device__ __forceinline__ uint32_t level_of(uint32_t node) { return 31u - (uint32_t)__clz(node); }
 
@@ -187,31 +192,32 @@ __device__ __forceinline__ void load_pair(const SlotDesc* d, uint32_t pa, uint32
 
 // Lower bound of the distance between triangles P and Q from three candidate
 // separating axes: the normal of P, the normal of Q, and the line through the
-// two centroids (a projection of both sets onto an axis never increases
-// distances).  Zero when no axis separates.
+// two centroids.  Both vertex sets are projected onto each axis and the gap
+// between the two intervals is the bound: a projection never increases
+// distances, whatever direction the axis has, so the FP32 rounding of a
+// normal's direction (large for slivers) cannot make the bound exceed the
+// distance; only the rounding of the projections themselves remains, which is
+// a few units of 2^-24 times the coordinates' magnitude, inside the error
+// window.  An axis whose squared length is not a normal float is skipped.
+// Zero when no axis separates.
+__device__ __forceinline__ float axis_gap(const V3<float>* P, const V3<float>* Q, V3<float> o, V3<float> n) {
+  const float p0 = dot(n, P[0] - o), p1 = dot(n, P[1] - o), p2 = dot(n, P[2] - o);
+  const float q0 = dot(n, Q[0] - o), q1 = dot(n, Q[1] - o), q2 = dot(n, Q[2] - o);
+  const float pmin = fminf(p0, fminf(p1, p2)), pmax = fmaxf(p0, fmaxf(p1, p2));
+  const float qmin = fminf(q0, fminf(q1, q2)), qmax = fmaxf(q0, fmaxf(q1, q2));
+  return fmaxf(qmin - pmax, pmin - qmax);
+}
 __device__ __forceinline__ float sep_lower(const V3<float>* P, const V3<float>* Q) {
   float lb = 0.f;
-  V3<float> n = cross(P[1] - P[0], P[2] - P[0]);
-  float nn = dot(n, n);
-  if (nn > 0.f) {
-    float s0 = dot(n, Q[0] - P[0]), s1 = dot(n, Q[1] - P[0]), s2 = dot(n, Q[2] - P[0]);
-    float s = fmaxf(fminf(s0, fminf(s1, s2)), -fmaxf(s0, fmaxf(s1, s2)));
-    lb = fmaxf(lb, s * rsqrtf(nn));
-  }
-  V3<float> m = cross(Q[1] - Q[0], Q[2] - Q[0]);
-  float mm = dot(m, m);
-  if (mm > 0.f) {
-    float s0 = dot(m, P[0] - Q[0]), s1 = dot(m, P[1] - Q[0]), s2 = dot(m, P[2] - Q[0]);
-    float s = fmaxf(fminf(s0, fminf(s1, s2)), -fmaxf(s0, fmaxf(s1, s2)));
-    lb = fmaxf(lb, s * rsqrtf(mm));
-  }
-  V3<float> u = (Q[0] + Q[1] + Q[2]) - (P[0] + P[1] + P[2]);
-  float uu = dot(u, u);
-  if (uu > 0.f) {
-    float pmax = fmaxf(dot(P[0], u), fmaxf(dot(P[1], u), dot(P[2], u)));
-    float qmin = fminf(dot(Q[0], u), fminf(dot(Q[1], u), dot(Q[2], u)));
-    lb = fmaxf(lb, (qmin - pmax) * rsqrtf(uu));
-  }
+  const V3<float> n = cross(P[1] - P[0], P[2] - P[0]);
+  const float nn = dot(n, n);
+  if (nn >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], n) * rsqrtf(nn));
+  const V3<float> m = cross(Q[1] - Q[0], Q[2] - Q[0]);
+  const float mm = dot(m, m);
+  if (mm >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], m) * rsqrtf(mm));
+  const V3<float> u = (Q[0] + Q[1] + Q[2]) - (P[0] + P[1] + P[2]);
+  const float uu = dot(u, u);
+  if (uu >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], u) * rsqrtf(uu));
   return lb;
 }
 
@@ -243,7 +249,7 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     M = fmaxf(M, fmaxf(fmaxf(fabsf(ra.lo[k]), fabsf(ra.hi[k])), fmaxf(fabsf(rb.lo[k]), fabsf(rb.hi[k]))));
-  M = fmaxf(M, 1e-30f);
+  M = fmaxf(fmaxf(M, d.m_floor), 1e-30f);
   const float delta = d.kappa_u * M;
   float key, best;
   if (mode == 0) {
@@ -540,7 +546,8 @@ __device__ __forceinline__ void append_rows(const bool* take, const uint4* e, ui
 // starts and bounds are wave-uniform.
 template <int R>
 __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base0,
-                                            uint32_t n_items, uint32_t kk, uint32_t lane, uint64_t lt, WaveStats& ws) {
+                                            uint32_t n_items, uint32_t kk, uint32_t lane, uint64_t lt, WaveStats& ws,
+                                            LaneStats& ls) {
   Ctl* c = p.ctl;
   uint4 ent[R];
   bool act[R];
@@ -580,6 +587,7 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
     a = a && (sub >> (kA + kB)) == 0u;
     add_stat(ws, ST_POPPED, a && sub == 0u);
     add_stat(ws, ST_CHILD, a);
+    ls.boxes += (a && sub == 0u) ? (1u << kA) + (1u << kB) : 0u;
     const uint32_t ca = (ent[r].x << kA) | (sub & ((1u << kA) - 1u));
     const uint32_t cb = (ent[r].y << kB) | (sub >> kA);
     bool keep = false;
@@ -661,7 +669,7 @@ __device__ __forceinline__ uint4 leaf_row(const BlockState* bs, const Round& rd,
 
 __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base,
                                                    uint32_t n_items, uint4 ent, uint32_t lane, uint64_t lt, uint4* q,
-                                                   uint32_t& qn, WaveStats& ws) {
+                                                   uint32_t& qn, WaveStats& ws, LaneStats& ls) {
   bool act = base + lane < n_items;
   const uint32_t slot = ent.w;
   const SlotView v = slot_view(p, bs, rd.lds_slots, act, slot);
@@ -674,6 +682,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
   if (act) {
     leaf_range(ent.x, v.depthA, v.nA, sa, ea);
     leaf_range(ent.y, v.depthB, v.nB, sb, eb);
+    ls.ltris += (ea - sa) + (eb - sb);
   }
   V3<float> P[2][3], Q[2][3];
   if (act) {
@@ -795,6 +804,9 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   WaveStats ws;
 #pragma unroll
   for (int i = 0; i < ST_N; ++i) ws.v[i] = 0u;
+  LaneStats ls;
+  ls.boxes = 0u;
+  ls.ltris = 0u;
   if (tid < ST_N) bs->stats[tid] = 0ull;
   if (tid == 0) {
     bs->fo = 0u;
@@ -873,9 +885,9 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
         if (w < leaf_waves) {
           const uint4 cur = lent;
           if (w + nw < leaf_waves) lent = leaf_row(bs, rd, (w + nw) * 64u, nl, lane);
-          narrow_filter_wave(p, bs, rd, w * 64u, nl, cur, lane, lt, q, qn, ws);
+          narrow_filter_wave(p, bs, rd, w * 64u, nl, cur, lane, lt, q, qn, ws, ls);
         } else if (w < spill_end) spill_wave(bs, rd, (w - leaf_waves) * 64u, lane);
-        else expand_rows<kRows>(p, bs, rd, (w - spill_end) * 64u * kRows, exp_items, kk, lane, lt, ws);
+        else expand_rows<kRows>(p, bs, rd, (w - spill_end) * 64u * kRows, exp_items, kk, lane, lt, ws, ls);
         w += nw;
       }
       while (qn >= 64u || (!more && qn > 0u)) {
@@ -887,6 +899,17 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
         narrow_full(p, bs, lds_slots, e, a, lane, lt, ws);
       }
       if (!more) break;
+    }
+    {
+      // the round's byte-count operands, summed per wave (kept per round so
+      // the per-lane 32-bit sums cannot wrap)
+      const uint32_t sb = wave_sum(ls.boxes), stt = wave_sum(ls.ltris);
+      if (lane == 0u) {
+        if (sb) atomicAdd(&bs->stats[ST_BOXES], (unsigned long long)sb);
+        if (stt) atomicAdd(&bs->stats[ST_LTRI], (unsigned long long)stt);
+      }
+      ls.boxes = 0u;
+      ls.ltris = 0u;
     }
     // publish this workgroup's output counts for the next round
     __syncthreads();
@@ -909,7 +932,8 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   }
   if (lane == 0)
     for (int i = 0; i < ST_N; ++i)
-      if (i != ST_ROUNDS && i != ST_PEAK && ws.v[i]) atomicAdd(&bs->stats[i], (unsigned long long)ws.v[i]);
+      if (i != ST_ROUNDS && i != ST_PEAK && i != ST_BOXES && i != ST_LTRI && ws.v[i])
+        atomicAdd(&bs->stats[i], (unsigned long long)ws.v[i]);
 
   __syncthreads();
   if (tid < ST_N && bs->stats[tid]) {

@@ -64,6 +64,33 @@ def run_stream(ctx: int, handles: Sequence[int], queries, max_slots: int = 64, r
     return {"results": results, "latency_ms": lat, "wall_s": wall, "stats": stats}
 
 
+def run_plain_stream(ctx: int, handles: Sequence[int], queries, time_scale: float = 1.0,
+                     timeout_s: float = 300.0) -> dict:
+    """The plain form under the same open-loop arrivals: one gdist_query per
+    query, issued at its arrival time (or as soon as the previous call
+    returns, if that is later).  Latency = completion - arrival, so it
+    includes the time a query waited behind earlier ones.  Returns
+    {"results", "latency_ms", "wall_s"}."""
+    n = len(queries)
+    results: List[dict] = []
+    lat = np.zeros(n)
+    t0 = time.perf_counter()
+    deadline = t0 + timeout_s
+    for i, q in enumerate(queries):
+        due = t0 + q.arrival * time_scale
+        while True:
+            now = time.perf_counter()
+            if now >= due:
+                break
+            if due - now > 0.0005:
+                time.sleep(0.0002)
+        results.append(gdist.gdist_query(ctx, handles[q.a], handles[q.b], q.pose_a, q.pose_b, q.mode))
+        lat[i] = (time.perf_counter() - due) * 1e3
+        if time.perf_counter() > deadline:
+            raise TimeoutError(f"plain stream finished {i + 1} of {n} queries in {timeout_s} s")
+    return {"results": results, "latency_ms": lat, "wall_s": time.perf_counter() - t0}
+
+
 def main(argv=None) -> int:
     import meshgen as g
 
@@ -107,10 +134,11 @@ def main(argv=None) -> int:
     return 0
 
 
-def compare(ctx: int, handles: Sequence[int], queries, served: List[dict]) -> dict:
+def compare(ctx: int, handles: Sequence[int], queries, served: List[dict] = None, keep_plain: bool = False) -> dict:
     """The same queries in the plain form (one gdist_query each, back to back)
-    and as one gdist_query_batch call; every served result must equal its
-    plain result (same FP64 distance bits and pair)."""
+    and as one gdist_query_batch call; every served result (if given) must
+    equal its plain result (same FP64 distance bits and pair).  keep_plain
+    adds the plain results under "plain_results"."""
     plain, lat = [], []
     t0 = time.perf_counter()
     for q in queries:
@@ -128,11 +156,15 @@ def compare(ctx: int, handles: Sequence[int], queries, served: List[dict]) -> di
         return r["distance"] == a["distance"] and (r["tri_a"], r["tri_b"]) == (a["tri_a"], a["tri_b"])
 
     lat = np.array(lat)
-    return {"plain_qps": round(len(queries) / plain_s, 2), "plain_p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "plain_p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "batch_qps": round(len(queries) / batch_s, 2), "batch_ms": round(batch_s * 1e3, 2),
-            "served_equal_plain": all(same(r, a) for r, a in zip(served, plain)),
-            "batch_equal_plain": all(same(r, a) for r, a in zip(batch, plain))}
+    out = {"plain_qps": round(len(queries) / plain_s, 2), "plain_p50_ms": round(float(np.percentile(lat, 50)), 3),
+           "plain_p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "batch_qps": round(len(queries) / batch_s, 2), "batch_ms": round(batch_s * 1e3, 2),
+           "batch_equal_plain": all(same(r, a) for r, a in zip(batch, plain))}
+    if served is not None:
+        out["served_equal_plain"] = all(same(r, a) for r, a in zip(served, plain))
+    if keep_plain:
+        out["plain_results"] = plain
+    return out
 
 
 if __name__ == "__main__":

@@ -5,16 +5,18 @@ Calls only the FP64 CPU oracle (oracle/) and the seeded input generators
 oracle's optimum, its canonical pair (lexicographically smallest pair within
 tau of the optimum), the size of that tie set and the tolerance tau.
 
-    python tests/golden/make_golden.py [rings] [hard_min] [hard_max] [batched]
+    python tests/golden/make_golden.py [rings] [hard_min] [hard_max] [batched] [batched_all] [serving]
 
 Writes tests/golden/<name>.json.  Run times on 8 host cores: rings about a
 minute, hard_min a few minutes, hard_max about ten minutes (10^12 vertex
-pairs), batched a few minutes.
+pairs), batched a few minutes, batched_all and serving some minutes each
+(independent queries run in parallel worker processes, one thread each).
 """
 import json
 import os
 import sys
 import time
+from concurrent.futures import ProcessPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -26,6 +28,12 @@ import oracle  # noqa: E402
 RINGS_FRAMES = [0, 37, 99]
 BATCHED_PAIRS = list(range(12))
 HARD = dict(seed=4, n=316)
+# serving stream (pool seed 2, 64 meshes; stream seed 3): the first 200
+# queries (about half in max mode, 10 overlapping, 15 on the largest mesh of
+# about 1.9M triangles)
+SERVING = dict(pool_seed=2, n_meshes=64, stream_seed=3, rate=5000.0, stream_len=200)
+SERVING_QUERIES = list(range(200))
+WORKERS = max(1, min(8, os.cpu_count() or 1))
 
 
 def record(name, mode, res, seconds, **extra):
@@ -81,8 +89,56 @@ def batched():
     write("batched_pairs", recs)
 
 
+def _one_query(args):
+    """One oracle query in a worker process (single thread): min mode by the
+    oracle's BVH (brute force for small pair counts), max mode by the BVH or,
+    for pairs whose max-mode culling is weak, by vertex pairs."""
+    va, fa, pa, vb, fb, pb, mode = args
+    t = time.time()
+    if mode == 0:
+        r = oracle.query(va, fa, pa, vb, fb, pb, 0, "auto", threads=1)
+    else:
+        r = oracle.query(va, fa, pa, vb, fb, pb, 1, "auto" if len(fa) * len(fb) <= 8_000_000 else "bvh",
+                         threads=1)
+    return r, time.time() - t
+
+
+def batched_all():
+    """Every pair of the 256-pair batched workload (seed 1)."""
+    jobs, meta = [], []
+    for p in range(256):
+        ma, mb, pa, pb, gap = g.batched_pair(1, p)
+        jobs.append((ma.verts, ma.tris, g.pose_to_flat(pa), mb.verts, mb.tris, g.pose_to_flat(pb), 0))
+        meta.append(dict(seed=1, pair=p, gap=gap, tris=[ma.n_tris, mb.n_tris]))
+    recs = []
+    with ProcessPoolExecutor(WORKERS) as ex:
+        for (r, dt), m in zip(ex.map(_one_query, jobs), meta):
+            recs.append(record("batched", 0, r, dt, **m))
+            print(recs[-1], flush=True)
+    write("batched_all", recs)
+
+
+def serving():
+    pool = g.serving_pool(SERVING["pool_seed"], SERVING["n_meshes"])
+    qs = g.serving_stream(pool, SERVING["rate"], SERVING["stream_len"], seed=SERVING["stream_seed"])
+    jobs, meta = [], []
+    for i in SERVING_QUERIES:
+        q = qs[i]
+        ma, mb = pool[q.a], pool[q.b]
+        jobs.append((ma.verts, ma.tris, g.pose_to_flat(q.pose_a), mb.verts, mb.tris, g.pose_to_flat(q.pose_b),
+                     q.mode))
+        meta.append(dict(query=i, a=q.a, b=q.b, gap=q.gap, tris=[ma.n_tris, mb.n_tris], **SERVING))
+    recs = []
+    with ProcessPoolExecutor(WORKERS) as ex:
+        for (r, dt), m, i in zip(ex.map(_one_query, jobs), meta, SERVING_QUERIES):
+            recs.append(record("serving", qs[i].mode, r, dt, **m))
+            print(recs[-1], flush=True)
+    write("serving_stream", recs)
+
+
 if __name__ == "__main__":
     oracle.build_oracle(force=False)
     todo = sys.argv[1:] or ["rings", "hard_min", "hard_max", "batched"]
     for job in todo:
-        {"rings": rings, "hard_min": lambda: hard(0), "hard_max": lambda: hard(1), "batched": batched}[job]()
+        {"rings": rings, "hard_min": lambda: hard(0), "hard_max": lambda: hard(1), "batched": batched,
+         "batched_all": batched_all, "serving": serving}[job]()

@@ -5,8 +5,10 @@ tests/golden/make_golden.py, which calls only the CPU oracle and the seeded
 generators.  The workloads are the full-size configurations: the Rings
 sequence (two 7.5M-triangle tori, frames 0, 37 and 99), the Hard pair (two
 concentric noisy geodesic spheres of about 2M triangles each, min and max),
-and the first twelve pairs of the batched workload (sizes log-uniform in
-[1e3, 5e5] triangles).
+the first twelve pairs of the batched workload (sizes log-uniform in
+[1e3, 5e5] triangles) and all 256 of its pairs in one call, and the first
+200 queries of the serving stream (64 resident meshes of 10K-2M triangles,
+half in max mode, some overlapping), served and batched.
 
 Bar: distance within 1e-6 absolute or 1e-5 relative of the oracle's; the
 reported pair is in the tie set (its own FP64 distance within tau of the
@@ -116,3 +118,68 @@ def test_batched_pairs(orc, gctx):
     finally:
         for h in handles:
             gdist.gdist_release(gctx, h)
+
+
+def test_batched_all_pairs(orc, gctx):
+    """All 256 pairs of the batched workload in one gdist_query_batch call
+    (the workload's launch shape) against the stored oracle results."""
+    recs = _load("batched_all")
+    assert len(recs) == 256
+    meshes, handles, descs = [], [], []
+    try:
+        for rec in recs:
+            ma, mb, pa, pb, gap = g.batched_pair(rec["seed"], rec["pair"])
+            assert [ma.n_tris, mb.n_tris] == rec["tris"]
+            ha, hb = gdist.gdist_build(gctx, ma.verts, ma.tris), gdist.gdist_build(gctx, mb.verts, mb.tris)
+            handles += [ha, hb]
+            meshes.append((ma, pa, mb, pb))
+            descs.append(gdist.make_desc(ha, hb, pa, pb, 0))
+        out = gdist.gdist_query_batch(gctx, descs)
+        for r, rec, (ma, pa, mb, pb) in zip(out, recs, meshes):
+            check_golden(orc, r, rec, ma, pa, mb, pb, 0)
+            assert r["distance"] >= rec["gap"] - 1e-9
+    finally:
+        for h in handles:
+            gdist.gdist_release(gctx, h)
+
+
+@pytest.fixture(scope="module")
+def serving_ctx():
+    """The serving configuration on a context of its own (its tuned launch
+    options stay off the shared context): 64 resident meshes of 10K-2M
+    triangles (pool seed 2) and the stored queries of its stream (seed 3)."""
+    from paper_2411_11244_amd import tune
+    recs = _load("serving_stream")
+    cfg = {k: recs[0][k] for k in ("pool_seed", "n_meshes", "stream_seed", "rate", "stream_len")}
+    pool = g.serving_pool(cfg["pool_seed"], cfg["n_meshes"])
+    qs = g.serving_stream(pool, cfg["rate"], cfg["stream_len"], seed=cfg["stream_seed"])
+    path = os.path.join(os.path.dirname(GOLDEN), "..", "paper_2411_11244_amd", "tuning", "serving_mi355x.json")
+    ctx = gdist.gdist_create(0)
+    try:
+        tune.apply(ctx, path)
+        handles = [gdist.gdist_build(ctx, m.verts, m.tris) for m in pool]
+        yield ctx, pool, handles, [qs[r["query"]] for r in recs], recs, tune.server_config(path)
+    finally:
+        gdist.gdist_destroy(ctx)
+
+
+def _check_serving(orc, out, pool, qs, recs):
+    for r, q, rec in zip(out, qs, recs):
+        assert (q.a, q.b, q.mode) == (rec["a"], rec["b"], rec["mode"])
+        check_golden(orc, r, rec, pool[q.a], q.pose_a, pool[q.b], q.pose_b, q.mode)
+
+
+def test_serving_stream_served(orc, serving_ctx):
+    """The stored stream queries, submitted at their Poisson arrival times to
+    the tuned continuous-batching server, against the oracle."""
+    from paper_2411_11244_amd.serve import run_stream
+    ctx, pool, handles, qs, recs, sc = serving_ctx
+    out = run_stream(ctx, handles, qs, sc.get("max_slots", 64), sc.get("rounds_per_step", 4), timeout_s=120)
+    _check_serving(orc, out["results"], pool, qs, recs)
+
+
+def test_serving_stream_batched(orc, serving_ctx):
+    """The same queries as one gdist_query_batch call, against the oracle."""
+    ctx, pool, handles, qs, recs, _ = serving_ctx
+    descs = [gdist.make_desc(handles[q.a], handles[q.b], q.pose_a, q.pose_b, q.mode) for q in qs]
+    _check_serving(orc, gdist.gdist_query_batch(ctx, descs), pool, qs, recs)
