@@ -137,6 +137,7 @@ typedef struct {
   uint64_t child_boxes;     /* child boxes read: sum of 2^kA + 2^kB over popped entries */
   uint64_t leaf_tris;       /* triangles read: sum of tA + tB over leaf pairs          */
   uint64_t bytes_reeval;    /* FP64 re-evaluation: 144 per candidate                   */
+  uint64_t refit_trees;     /* trees refitted by the call                              */
 } gdist_stats_t;
 
 /* ---------------------------------------------------------------- context */
@@ -239,6 +240,9 @@ gdist_status_t gdist_query(gdist_ctx_t ctx, gdist_mesh_t a, gdist_mesh_t b,
  * returns for it alone.  out[i].status carries the per-query status (a query
  * that could not complete, e.g. after E_CAPACITY, holds that status and a NaN
  * distance); the call returns the first non-OK status, or OK.  Synchronous. */
+gdist_status_t gdist_query_batch(gdist_ctx_t ctx, uint32_t n, const gdist_query_desc_t* q,
+                                 gdist_result_t* out);
+
 /* One mesh against n others (the paper's future work, Sec. 8): mesh a at
  * pose pa against b[i] at pose pb[i], all in one batched call, result i in
  * out[i] (same per-query statuses and return value as gdist_query_batch).
@@ -246,9 +250,6 @@ gdist_status_t gdist_query(gdist_ctx_t ctx, gdist_mesh_t a, gdist_mesh_t b,
 gdist_status_t gdist_query_one_to_many(gdist_ctx_t ctx, gdist_mesh_t a, const gdist_pose_t* pa, uint32_t n,
                                        const gdist_mesh_t* b, const gdist_pose_t* pb, gdist_mode_t mode,
                                        gdist_result_t* out);
-
-gdist_status_t gdist_query_batch(gdist_ctx_t ctx, uint32_t n, const gdist_query_desc_t* q,
-                                 gdist_result_t* out);
 
 /* gdist_query_batch without waiting: the queries are validated (E_HANDLE /
  * E_INVALID now) and copied, then run in submission order by a worker thread

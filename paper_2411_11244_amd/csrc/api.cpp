@@ -391,19 +391,18 @@ gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx
       d.hint_b = it->second.second;
     }
   }
-  // The FP32 transform of B's vertices into A's frame rounds R, t and three
-  // fused multiply-adds per coordinate; its error grows with |x_B| (B's local
-  // coordinates, up to sqrt(3) max|B root| after the rotation) and |t|, which
-  // can far exceed the query frame's coordinates when they cancel.  M for the
-  // error window is at least that.
+  // The FP32 transform of B's vertices into A's frame rounds R and t (each
+  // entry to within 2^-24 relative) and three fused multiply-adds per
+  // coordinate.  With unit rows of R, every term and partial sum is at most
+  // |x_B| + |t| in magnitude, so a coordinate's error is a few units of 2^-24
+  // times |x_B| + |t|: B's largest local vertex norm plus the translation,
+  // which can far exceed the query frame's coordinates when they cancel.  M
+  // for the error window is at least that.
   {
-    double ma = 0.0, mb = 0.0, mt = 0.0;
-    for (int k = 0; k < 6; ++k) {
-      ma = std::fmax(ma, std::fabs((double)A->root[k]));
-      mb = std::fmax(mb, std::fabs((double)B->root[k]));
-    }
-    for (int k = 0; k < 3; ++k) mt = std::fmax(mt, std::fabs((double)d.T.t[k]));
-    d.m_floor = (float)std::fmax(ma, std::sqrt(3.0) * mb + mt);
+    double ma = 0.0, tt = 0.0;
+    for (int k = 0; k < 6; ++k) ma = std::fmax(ma, std::fabs((double)A->root[k]));
+    for (int k = 0; k < 3; ++k) tt += (double)d.T.t[k] * (double)d.T.t[k];
+    d.m_floor = (float)(std::fmax(ma, (double)B->rmax + std::sqrt(tt)) * (1.0 + 0x1p-20));
   }
   double M = std::fmax(world_extent(A->root, PA), world_extent(B->root, PB));
   d.tau = 1e-12 * std::fmax(1.0, M);
@@ -411,11 +410,6 @@ gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx
   *Bout = B;
   return GDIST_OK;
 }
-
-struct SlotPlan {
-  Mesh* B;
-  size_t box_off;  // float offset of B's refitted boxes in ws_boxes
-};
 
 // The query workspace is a cache that grows on demand.  When a query call
 // runs out of device memory (the budget or the device), the whole cache is
@@ -425,9 +419,186 @@ void release_workspace(gdist_ctx* c) {
   DevBuf* bufs[] = {&c->refit_tab, &c->ws_boxes, &c->front[0], &c->front[1], &c->leaf[0], &c->leaf[1], &c->stack,
                     &c->counts, &c->cand, &c->cand64, &c->ctl, &c->desc, &c->st, &c->res};
   for (DevBuf* b : bufs) release_buf(c, *b);
+  for (auto& kv : c->world)
+    for (auto& w : kv.second) release_buf(c, w.boxes);
+  c->world.clear();
 }
 
-gdist_status_t run_queries_impl(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out);
+// World-frame trees of the static side of one-to-many calls
+// (gdist_query_one_to_many): per mesh, the boxes of its tree refitted under
+// the poses it was last queried at (a few, most recent last).
+constexpr size_t kWorldPosesPerMesh = 4;
+
+void drop_world_trees(gdist_ctx* c, gdist_mesh_t h) {
+  auto it = c->world.find(h);
+  if (it == c->world.end()) return;
+  (void)hipStreamSynchronize(c->stream);   // no work in flight still reads them
+  for (auto& w : it->second) release_buf(c, w.boxes);
+  c->world.erase(it);
+}
+
+// What one query call runs: the slot descriptors and the refits ahead of the traversal.
+struct CallPlan {
+  std::vector<SlotDesc> desc;
+  std::vector<RefitJob> jobs;
+};
+
+// Pairwise plan: each query refits its smaller mesh into the larger one's
+// local frame (a box region of its own in ws_boxes).
+gdist_status_t plan_pairwise(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, CallPlan& cp) {
+  cp.desc.assign(n, SlotDesc{});
+  std::vector<Mesh*> Bs(n);
+  std::vector<size_t> off(n);
+  size_t box_floats = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    gdist_status_t s = make_slot(c, q[i], i, &cp.desc[i], &Bs[i]);
+    if (s != GDIST_OK) return s;
+    off[i] = box_floats;
+    box_floats += 6ull * 2ull * Bs[i]->L;
+    box_floats = (box_floats + 63) & ~(size_t)63;
+  }
+  gdist_status_t s = ensure(c, c->ws_boxes, box_floats * sizeof(float));
+  if (s != GDIST_OK) return s;
+  cp.jobs.assign(n, RefitJob{});
+  for (uint32_t i = 0; i < n; ++i) {
+    cp.desc[i].boxB = (const float*)c->ws_boxes.p + off[i];
+    RefitJob& j = cp.jobs[i];
+    std::memset(&j, 0, sizeof(j));
+    j.tris = Bs[i]->tris;
+    j.boxes = (float*)c->ws_boxes.p + off[i];
+    j.T = cp.desc[i].T;
+    j.n = Bs[i]->n_tris;
+    j.L = Bs[i]->L;
+  }
+  return GDIST_OK;
+}
+
+Xf32 pose_f32(const gdist_pose_t& P) {
+  Xf32 T;
+  for (int k = 0; k < 9; ++k) T.R[k] = (float)P.R[k];
+  for (int k = 0; k < 3; ++k) T.t[k] = (float)P.t[k];
+  return T;
+}
+
+// Shared plan (one mesh against many, Sec. 8 future work): the query frame is
+// the world.  Mesh a is refitted into it once for the whole call; each mesh
+// b[i] uses its world-frame tree under pose pb[i], kept by the context from
+// an earlier call with the same pose, or refitted in this call.  In every
+// slot b[i] is the static side ("A", its triangles transformed by its pose in
+// the narrow phase) and a the refitted side ("B").
+gdist_status_t plan_shared(gdist_ctx* c, gdist_mesh_t a, const gdist_pose_t& pa, uint32_t n, const gdist_mesh_t* b,
+                           const gdist_pose_t* pb, uint32_t mode, CallPlan& cp) {
+  Mesh* ma = find_mesh(c, a);
+  if (!ma) return fail(GDIST_E_HANDLE, "unknown mesh handle %llu", (unsigned long long)a);
+  if (mode > 1) return fail(GDIST_E_INVALID, "unknown mode %u", mode);
+  gdist_status_t s = check_pose(&pa, "a");
+  if (s != GDIST_OK) return s;
+  std::vector<Mesh*> mb(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    mb[i] = find_mesh(c, b[i]);
+    if (!mb[i]) return fail(GDIST_E_HANDLE, "query %u: unknown mesh handle", i);
+    if ((s = check_pose(&pb[i], "b")) != GDIST_OK) return s;
+  }
+  // a's world-frame tree for this call
+  if ((s = ensure(c, c->ws_boxes, 48ull * ma->L)) != GDIST_OK) return s;
+  cp.jobs.clear();
+  const Xf32 Ta = pose_f32(pa);
+  {
+    RefitJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.tris = ma->tris;
+    j.boxes = (float*)c->ws_boxes.p;
+    j.T = Ta;
+    j.n = ma->n_tris;
+    j.L = ma->L;
+    cp.jobs.push_back(j);
+  }
+  // the static side's world-frame trees: kept, or refitted now
+  std::vector<const float*> wb(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    auto& lst = c->world[b[i]];
+    gdist_ctx::WorldTree* hit = nullptr;
+    for (auto& w : lst)
+      if (std::memcmp(&w.pose, &pb[i], sizeof(gdist_pose_t)) == 0) hit = &w;
+    if (!hit) {
+      if (lst.size() >= kWorldPosesPerMesh) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        release_buf(c, lst.front().boxes);
+        lst.erase(lst.begin());
+      }
+      gdist_ctx::WorldTree w;
+      w.pose = pb[i];
+      if ((s = ensure(c, w.boxes, 48ull * mb[i]->L)) != GDIST_OK) return s;
+      lst.push_back(w);
+      hit = &lst.back();
+      RefitJob j;
+      std::memset(&j, 0, sizeof(j));
+      j.tris = mb[i]->tris;
+      j.boxes = (float*)hit->boxes.p;
+      j.T = pose_f32(pb[i]);
+      j.n = mb[i]->n_tris;
+      j.L = mb[i]->L;
+      cp.jobs.push_back(j);
+    }
+    wb[i] = (const float*)hit->boxes.p;
+  }
+  double ta = 0.0;
+  for (int k = 0; k < 3; ++k) ta += (double)Ta.t[k] * (double)Ta.t[k];
+  cp.desc.assign(n, SlotDesc{});
+  for (uint32_t i = 0; i < n; ++i) {
+    const Mesh* A = mb[i];
+    SlotDesc& d = cp.desc[i];
+    std::memset(&d, 0, sizeof(d));
+    d.boxA = wb[i];
+    d.boxB = (const float*)c->ws_boxes.p;
+    d.trisA = A->tris;
+    d.trisB = ma->tris;
+    d.origA = A->orig;
+    d.origB = ma->orig;
+    d.nA = A->n_tris;
+    d.nB = ma->n_tris;
+    d.LA = A->L;
+    d.LB = ma->L;
+    d.depthA = A->depth;
+    d.depthB = ma->depth;
+    d.mode = mode;
+    d.enhanced = c->bounds == 0 ? 1u : 0u;
+    d.swapped = 1u;   // the caller's mesh a is the refitted side
+    d.kappa_u = (float)(c->kappa * std::ldexp(1.0, -24));
+    d.T = Ta;
+    d.TA = pose_f32(pb[i]);
+    d.xfA = 1u;
+    for (int k = 0; k < 9; ++k) {
+      d.RA[k] = pb[i].R[k];
+      d.RB[k] = pa.R[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+      d.tA[k] = pb[i].t[k];
+      d.tB[k] = pa.t[k];
+    }
+    // both sides are transformed in FP32 (see make_slot): M is at least each
+    // side's largest local vertex norm plus its translation
+    double tb = 0.0;
+    for (int k = 0; k < 3; ++k) tb += (double)d.TA.t[k] * (double)d.TA.t[k];
+    d.m_floor = (float)(std::fmax((double)A->rmax + std::sqrt(tb), (double)ma->rmax + std::sqrt(ta)) * (1.0 + 0x1p-20));
+    double M = std::fmax(world_extent(A->root, pb[i]), world_extent(ma->root, pa));
+    d.tau = 1e-12 * std::fmax(1.0, M);
+    d.err_bound = 1e-13 * std::fmax(1.0, M);
+  }
+  return GDIST_OK;
+}
+
+gdist_status_t execute_plan(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, CallPlan& cp,
+                            gdist_result_t* out);
+
+gdist_status_t run_queries_impl(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out) {
+  if (n == 0) return GDIST_OK;
+  if (!q || !out) return fail(GDIST_E_INVALID, "NULL query or result array");
+  CallPlan cp;
+  gdist_status_t s = plan_pairwise(c, n, q, cp);
+  if (s != GDIST_OK) return s;
+  return execute_plan(c, n, q, cp, out);
+}
 
 gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out) {
   gdist_status_t s = run_queries_impl(c, n, q, out);
@@ -439,41 +610,20 @@ gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q
   return s;
 }
 
-gdist_status_t run_queries_impl(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out) {
-  if (n == 0) return GDIST_OK;
-  if (!q || !out) return fail(GDIST_E_INVALID, "NULL query or result array");
-  std::vector<SlotDesc> desc(n);
-  std::vector<SlotPlan> plan(n);
-  size_t box_floats = 0;
-  for (uint32_t i = 0; i < n; ++i) {
-    Mesh* B = nullptr;
-    gdist_status_t s = make_slot(c, q[i], i, &desc[i], &B);
-    if (s != GDIST_OK) return s;
-    plan[i].B = B;
-    plan[i].box_off = box_floats;
-    box_floats += 6ull * 2ull * B->L;
-    box_floats = (box_floats + 63) & ~(size_t)63;
-  }
-  gdist_status_t s = ensure(c, c->ws_boxes, box_floats * sizeof(float));
-  if (s != GDIST_OK) return s;
-  for (uint32_t i = 0; i < n; ++i) desc[i].boxB = (const float*)c->ws_boxes.p + plan[i].box_off;
+// Upload, refits, traversal in groups of slots, FP64 re-evaluation, stats.
+// q (optional) names the caller's meshes of each slot for the warm start.
+gdist_status_t execute_plan(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, CallPlan& cp,
+                            gdist_result_t* out) {
+  gdist_status_t s;
+  std::vector<SlotDesc>& desc = cp.desc;
+  const uint32_t njobs = (uint32_t)cp.jobs.size();
   if ((s = ensure(c, c->desc, sizeof(SlotDesc) * n)) != GDIST_OK) return s;
   if ((s = ensure(c, c->st, sizeof(SlotState) * n)) != GDIST_OK) return s;
   if ((s = ensure(c, c->res, sizeof(gdist_result_t) * n)) != GDIST_OK) return s;
   if ((s = ensure(c, c->ctl, sizeof(Ctl))) != GDIST_OK) return s;
   // descriptors and refit job tables go through pinned staging (async H2D)
-  std::vector<RefitJob> jobs(n);
-  for (uint32_t i = 0; i < n; ++i) {
-    const Mesh* B = plan[i].B;
-    std::memset(&jobs[i], 0, sizeof(RefitJob));
-    jobs[i].tris = B->tris;
-    jobs[i].boxes = (float*)c->ws_boxes.p + plan[i].box_off;
-    jobs[i].T = desc[i].T;
-    jobs[i].n = B->n_tris;
-    jobs[i].L = B->L;
-  }
   const size_t desc_bytes = (sizeof(SlotDesc) * n + 255) & ~(size_t)255;
-  const size_t tab_cap = sizeof(RefitJob) * n + sizeof(ReduceJob) * n * kMaxRefitPasses + 256;
+  const size_t tab_cap = sizeof(RefitJob) * njobs + sizeof(ReduceJob) * njobs * kMaxRefitPasses + 256;
   // copy-back area after the tables: control block, results, slot states
   const auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
   c->back_off = al(desc_bytes + tab_cap);
@@ -482,8 +632,8 @@ gdist_status_t run_queries_impl(gdist_ctx* c, uint32_t n, const gdist_query_desc
   if ((s = ensure_pinned(c, c->back_off + c->back_st + sizeof(SlotState) * n)) != GDIST_OK) return s;
   std::memcpy(c->pinned, desc.data(), sizeof(SlotDesc) * n);
   RefitPlan rplan;
-  const size_t tab_bytes = plan_refit_batch(jobs.data(), n, (char*)c->pinned + desc_bytes, tab_cap, &rplan);
-  if (tab_bytes == 0) return fail(GDIST_E_INVALID, "refit plan does not fit (%u queries)", n);
+  const size_t tab_bytes = plan_refit_batch(cp.jobs.data(), njobs, (char*)c->pinned + desc_bytes, tab_cap, &rplan);
+  if (tab_bytes == 0) return fail(GDIST_E_INVALID, "refit plan does not fit (%u trees)", njobs);
   if ((s = ensure(c, c->refit_tab, tab_bytes)) != GDIST_OK) return s;
   HIPCHK(hipMemcpyAsync(c->desc.p, c->pinned, sizeof(SlotDesc) * n, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->refit_tab.p, (char*)c->pinned + desc_bytes, tab_bytes, hipMemcpyHostToDevice, c->stream));
@@ -491,7 +641,8 @@ gdist_status_t run_queries_impl(gdist_ctx* c, uint32_t n, const gdist_query_desc
   std::memset(&c->last, 0, sizeof(c->last));
   HIPCHK(hipEventRecord(c->ev[0], c->stream));
   HIPCHK(launch_refit_batch(rplan, c->refit_tab.p, c->stream));
-  for (uint32_t i = 0; i < n; ++i) c->last.bytes_refit += 36ull * plan[i].B->n_tris + 24ull * (2ull * plan[i].B->L - 1ull);
+  for (const RefitJob& j : cp.jobs) c->last.bytes_refit += 36ull * j.n + 24ull * (2ull * j.L - 1ull);
+  c->last.refit_trees = njobs;
   HIPCHK(hipEventRecord(c->ev[1], c->stream));
 
   // Traversal in groups of slots.  A group whose storage overflows first
@@ -499,7 +650,8 @@ gdist_status_t run_queries_impl(gdist_ctx* c, uint32_t n, const gdist_query_desc
   // still does not fit is split in half, and later calls on this context
   // start from the smaller group size.
   std::memset(&c->last_ctl_sum, 0, sizeof(c->last_ctl_sum));
-  if (c->warm_start) c->warm_st.assign(n, SlotState{});
+  const bool warm = c->warm_start && q;
+  if (warm) c->warm_st.assign(n, SlotState{});
   uint32_t group = (c->group_hint && c->group_hint < n) ? c->group_hint : n;
   if (c->group_size && c->group_size < group) group = c->group_size;
   bool first_launch = true;
@@ -523,7 +675,7 @@ gdist_status_t run_queries_impl(gdist_ctx* c, uint32_t n, const gdist_query_desc
     }
     g0 += gn;
   }
-  if (c->warm_start) {
+  if (warm) {
     // remember each query's reported pair (leaf positions) for the next query of its meshes
     for (uint32_t i = 0; i < n; ++i)
       if (out[i].status == GDIST_OK && c->warm_st[i].pair_a != ~0u)
@@ -637,6 +789,7 @@ gdist_status_t gdist_set_option(gdist_ctx_t c, const char* key, double v) {
   if (k == "expand_budget") return u32opt(&c->expand_budget, 4, 1u << 30);
   if (k == "k_cap") return u32opt(&c->k_cap, 1, 8);
   if (k == "bounds") return u32opt(&c->bounds, 0, 1);
+  if (k == "one_to_many") return u32opt(&c->one_to_many, 0, 2);
   if (k == "warm_start") {
     gdist_status_t st = u32opt(&c->warm_start, 0, 1);
     if (st == GDIST_OK && !c->warm_start) c->warm.clear();
@@ -727,24 +880,29 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
     TRYHIP(hipMemcpyAsync(df, tris, fb, hipMemcpyHostToDevice, c->stream));
   }
   TRY(dalloc(c, 64, &misc));
-  int* cbox = (int*)misc;
+  TRY(dalloc(c, 8ull * nt, &keys));
+  TRY(dalloc(c, 4ull * nt, &vals));
+  int* vbox = (int*)misc;
   uint32_t* vflags = (uint32_t*)((char*)misc + 32);
-  TRYHIP(launch_validate_centroids((const float*)dv, nv, (const uint32_t*)df, nt, cbox, vflags, c->stream));
+  // vertex pass and key pass; the keys are used only once both checks passed
+  TRYHIP(launch_vertex_pass((const float*)dv, nv, vbox, vflags, c->stream));
+  TRYHIP(launch_keys((const float*)dv, nv, (const uint32_t*)df, nt, vbox, (uint64_t*)keys, (uint32_t*)vals, vflags,
+                     c->stream));
   uint32_t hflags = 0;
+  int hrmax = 0;
   TRYHIP(hipMemcpyAsync(&hflags, vflags, 4, hipMemcpyDeviceToHost, c->stream));
+  TRYHIP(hipMemcpyAsync(&hrmax, vbox + 6, 4, hipMemcpyDeviceToHost, c->stream));
   TRYHIP(hipStreamSynchronize(c->stream));
+  std::memcpy(&m->rmax, &hrmax, 4);   // a non-negative float: its ordered int is its bits
   if (hflags & 1u) return abort_build(fail(GDIST_E_INVALID, "a triangle index is >= n_verts (%u)", nv));
   if (hflags & 2u) return abort_build(fail(GDIST_E_INVALID, "a vertex coordinate is not finite"));
-  TRY(dalloc(c, 8ull * nt, &keys));
   TRY(dalloc(c, 8ull * nt, &keys2));
-  TRY(dalloc(c, 4ull * nt, &vals));
   TRY(dalloc(c, 4ull * nt, &vals2));
   TRY(dalloc(c, hb, &hist));
   TRY(dalloc(c, 36ull * nt, (void**)&m->tris));
   TRY(dalloc(c, 4ull * nt, (void**)&m->orig));
   TRY(dalloc(c, 48ull * m->L, (void**)&m->boxes));
   if (deformable) TRY(dalloc(c, 12ull * nt, (void**)&m->fl));
-  TRYHIP(launch_morton((const float*)dv, (const uint32_t*)df, nt, cbox, (uint64_t*)keys, (uint32_t*)vals, c->stream));
   int in_tmp = 0;
   TRYHIP(launch_radix_sort((uint64_t*)keys, (uint32_t*)vals, (uint64_t*)keys2, (uint32_t*)vals2, nt,
                            (uint32_t*)hist, c->stream, &in_tmp));
@@ -777,6 +935,7 @@ gdist_status_t gdist_release(gdist_ctx_t c, gdist_mesh_t h) {
   HIPCHK(hipStreamSynchronize(c->stream));
   free_mesh(c, m);
   c->meshes.erase(h);
+  drop_world_trees(c, h);
   for (auto it = c->warm.begin(); it != c->warm.end();)
     it = (it->first.a == h || it->first.b == h) ? c->warm.erase(it) : std::next(it);
   return GDIST_OK;
@@ -803,13 +962,16 @@ gdist_status_t gdist_update(gdist_ctx_t c, gdist_mesh_t h, const float* verts, u
   if ((s = dalloc(c, 64, &misc)) == GDIST_OK) {
     hipError_t e = hipSuccess;
     if (!(flags & GDIST_BUILD_DEVICE_PTR)) e = hipMemcpyAsync(dv, verts, vb, hipMemcpyHostToDevice, c->stream);
-    // finiteness (and, again, the indices) before anything of the mesh changes
+    // finiteness before anything of the mesh changes (the leaf-order indices
+    // were checked when the mesh was built)
     uint32_t hflags = 0;
     uint32_t* vflags = (uint32_t*)((char*)misc + 32);
-    if (e == hipSuccess)
-      e = launch_validate_centroids((const float*)dv, nv, m->fl, m->n_tris, (int*)misc, vflags, c->stream);
+    if (e == hipSuccess) e = launch_vertex_pass((const float*)dv, nv, (int*)misc, vflags, c->stream);
+    int hrmax = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hflags, vflags, 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&hrmax, (int*)misc + 6, 4, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && !(hflags & 3u)) std::memcpy(&m->rmax, &hrmax, 4);
     if (e != hipSuccess) {
       s = fail(GDIST_E_DEVICE, "mesh update failed: %s", hipGetErrorString(e));
     } else if (hflags & 3u) {
@@ -829,6 +991,7 @@ gdist_status_t gdist_update(gdist_ctx_t c, gdist_mesh_t h, const float* verts, u
   (void)hipStreamSynchronize(c->stream);
   if (!(flags & GDIST_BUILD_DEVICE_PTR)) dfree(c, dv, vb);
   dfree(c, misc, 64);
+  if (s == GDIST_OK) drop_world_trees(c, h);   // refitted from the old vertices
   return s;
 }
 
@@ -902,7 +1065,29 @@ gdist_status_t gdist_query_one_to_many(gdist_ctx_t c, gdist_mesh_t a, const gdis
   }
   drain_async(c);
   HIPCHK(hipSetDevice(c->device));
-  return run_queries(c, n, q.data(), out);
+  // Shared refit (a once, into the world frame; b[i] from kept world-frame
+  // trees) when it refits fewer triangles per call than the pairwise plan,
+  // whose query i refits the smaller of a and b[i]; pairwise otherwise.
+  bool shared = c->one_to_many == 2u;
+  if (c->one_to_many == 1u && n > 1) {
+    Mesh* ma = find_mesh(c, a);
+    uint64_t pairwise = 0;
+    for (uint32_t i = 0; i < n && ma; ++i) {
+      Mesh* mb = find_mesh(c, b[i]);
+      if (mb) pairwise += std::min(ma->n_tris, mb->n_tris);
+    }
+    shared = ma && (uint64_t)ma->n_tris < pairwise;
+  }
+  if (!shared) return run_queries(c, n, q.data(), out);
+  CallPlan cp;
+  gdist_status_t s = plan_shared(c, a, *pa, n, b, pb, (uint32_t)mode, cp);
+  if (s == GDIST_OK) s = execute_plan(c, n, nullptr, cp, out);
+  if (s == GDIST_E_OOM) {
+    std::string msg = t_err;
+    release_workspace(c);
+    t_err = msg;
+  }
+  return s;
 }
 
 gdist_status_t gdist_query_batch_async(gdist_ctx_t c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out,

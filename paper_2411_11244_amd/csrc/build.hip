@@ -4,9 +4,11 @@
 // implicitly in heap order.  The node boxes are produced by the refit kernels
 // with the identity transform.
 //
-// Kernels here: input validation + centroid bounds, Morton keys (63 bits,
-// 21 per axis), a stable LSD radix sort of (u64 key, u32 value) pairs with
-// 8-bit digits, and the scatter of triangles into leaf order.
+// Kernels here: a vertex pass (finiteness, vertex box, largest vertex norm),
+// a key pass (index check and the 63-bit Morton code of each centroid, 21
+// bits per axis, in the vertex box), a stable LSD radix sort of (u64 key, u32
+// value) pairs with 8-bit digits, and the scatter of triangles into leaf
+// order.
 #include "internal.hpp"
 
 namespace gd {
@@ -23,67 +25,71 @@ __host__ __device__ inline float unordered(int i) {
   return f;
 }
 
-// flags: bit 0 = index out of range, bit 1 = non-finite vertex.
-// cbox: 6 ints (ordered floats): centroid min xyz, centroid max xyz.
-__global__ void k_validate_centroids(const float* __restrict__ v, uint32_t nv, const uint32_t* __restrict__ f,
-                                     uint32_t nt, int* __restrict__ cbox, uint32_t* __restrict__ flags) {
+// Wave-wide reductions (every lane active).
+__device__ __forceinline__ float wave_max_reduce(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_min_reduce(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Vertex pass.  vb: 7 ints (ordered floats): vertex box min xyz, max xyz,
+// and an upper bound of the largest vertex norm |x|.  flags: bit 1 = a
+// non-finite vertex.  One reduction per workgroup, one atomic per value.
+constexpr int kVpThreads = 256;
+__global__ __launch_bounds__(kVpThreads) void k_vertex_pass(const float* __restrict__ v, uint32_t nv,
+                                                            int* __restrict__ vb, uint32_t* __restrict__ flags) {
   float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
   float hi[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
+  float rmax = 0.f;
   uint32_t bad = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
-    float x = v[3 * i], y = v[3 * i + 1], z = v[3 * i + 2];
-    if (!(isfinite(x) && isfinite(y) && isfinite(z))) bad |= 2u;
-  }
-  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
-    uint32_t i0 = f[3 * t], i1 = f[3 * t + 1], i2 = f[3 * t + 2];
-    if (i0 >= nv || i1 >= nv || i2 >= nv) {
-      bad |= 1u;
+    const float x = v[3 * i], y = v[3 * i + 1], z = v[3 * i + 2];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+      bad = 2u;
       continue;
     }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      float c = (v[3ull * i0 + k] + v[3ull * i1 + k] + v[3ull * i2 + k]) * (1.0f / 3.0f);
-      lo[k] = fminf(lo[k], c);
-      hi[k] = fmaxf(hi[k], c);
-    }
+    lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
+    hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
+    rmax = fmaxf(rmax, sqrtf(x * x + y * y + z * z));
   }
-  __shared__ float s_lo[3][256], s_hi[3][256];
-  __shared__ uint32_t s_bad;
-  if (threadIdx.x == 0) s_bad = 0;
-  __syncthreads();
-  if (bad) atomicOr(&s_bad, bad);
+  // a few roundings of relative size 2^-24 each: widen by 2^-20
+  float r[7];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    s_lo[k][threadIdx.x] = lo[k];
-    s_hi[k][threadIdx.x] = hi[k];
+    r[k] = wave_min_reduce(lo[k]);
+    r[3 + k] = wave_max_reduce(hi[k]);
   }
+  r[6] = wave_max_reduce(rmax) * (1.0f + 0x1p-20f);
+  __shared__ float sr[kVpThreads / 64][7];
+  __shared__ uint32_t s_bad;
+  if (threadIdx.x == 0) s_bad = 0u;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+  if (bad) atomicOr(&s_bad, bad);
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0u)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        s_lo[k][threadIdx.x] = fminf(s_lo[k][threadIdx.x], s_lo[k][threadIdx.x + s]);
-        s_hi[k][threadIdx.x] = fmaxf(s_hi[k][threadIdx.x], s_hi[k][threadIdx.x + s]);
-      }
-    }
-    __syncthreads();
+    for (int k = 0; k < 7; ++k) sr[w][k] = r[k];
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    const int k = threadIdx.x;
+    float a = sr[0][k];
+    for (int q = 1; q < kVpThreads / 64; ++q) a = k < 3 ? fminf(a, sr[q][k]) : fmaxf(a, sr[q][k]);
+    if (k < 3) atomicMin(&vb[k], ordered(a));
+    else atomicMax(&vb[k], ordered(a));
   }
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      atomicMin(&cbox[k], ordered(s_lo[k][0]));
-      atomicMax(&cbox[3 + k], ordered(s_hi[k][0]));
-    }
-    if (s_bad) atomicOr(flags, s_bad);
-  }
+  if (threadIdx.x == 0 && s_bad) atomicOr(flags, s_bad);
 }
 
-__global__ void k_init_cbox(int* cbox, uint32_t* flags) {
+__global__ void k_init_vb(int* vb, uint32_t* flags) {
   if (threadIdx.x < 3) {
-    cbox[threadIdx.x] = ordered(__builtin_huge_valf());
-    cbox[3 + threadIdx.x] = ordered(-__builtin_huge_valf());
+    vb[threadIdx.x] = ordered(__builtin_huge_valf());
+    vb[3 + threadIdx.x] = ordered(-__builtin_huge_valf());
   }
+  if (threadIdx.x == 3) vb[6] = 0;
   if (threadIdx.x == 0) *flags = 0;
 }
 
@@ -98,21 +104,28 @@ __device__ __forceinline__ uint64_t spread3(uint64_t x) {
   return x;
 }
 
-__global__ void k_morton(const float* __restrict__ v, const uint32_t* __restrict__ f, uint32_t nt,
-                         const int* __restrict__ cbox, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Key pass, one thread per triangle: the index check (flags bit 0) and the
+// 63-bit Morton code of the FP32 centroid, normalised to the vertex box.
+__global__ void k_keys(const float* __restrict__ v, uint32_t nv, const uint32_t* __restrict__ f, uint32_t nt,
+                       const int* __restrict__ vb, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                       uint32_t* __restrict__ flags) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
+  const uint32_t i0 = f[3 * t], i1 = f[3 * t + 1], i2 = f[3 * t + 2];
   uint64_t code = 0;
+  if (i0 >= nv || i1 >= nv || i2 >= nv) {
+    atomicOr(flags, 1u);
+  } else {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    float lo = unordered(cbox[k]), hi = unordered(cbox[3 + k]);
-    uint32_t i0 = f[3 * t], i1 = f[3 * t + 1], i2 = f[3 * t + 2];
-    float c = (v[3ull * i0 + k] + v[3ull * i1 + k] + v[3ull * i2 + k]) * (1.0f / 3.0f);
-    float ext = hi - lo;
-    float u = ext > 0.f ? (c - lo) / ext : 0.f;
-    float s = u * 2097152.0f;  // 2^21 cells per axis
-    uint32_t q = s <= 0.f ? 0u : (s >= 2097151.0f ? 2097151u : (uint32_t)s);
-    code |= spread3(q) << (2 - k);   // x on the highest of each bit triple
+    for (int k = 0; k < 3; ++k) {
+      const float lo = unordered(vb[k]), hi = unordered(vb[3 + k]);
+      const float c = (v[3ull * i0 + k] + v[3ull * i1 + k] + v[3ull * i2 + k]) * (1.0f / 3.0f);
+      const float ext = hi - lo;
+      const float u = ext > 0.f ? (c - lo) / ext : 0.f;
+      const float sc = u * 2097152.0f;  // 2^21 cells per axis
+      const uint32_t q = sc <= 0.f ? 0u : (sc >= 2097151.0f ? 2097151u : (uint32_t)sc);
+      code |= spread3(q) << (2 - k);   // x on the highest of each bit triple
+    }
   }
   keys[t] = code;
   vals[t] = (uint32_t)t;
@@ -303,20 +316,18 @@ __global__ void k_gather_tris(const float* __restrict__ v, const uint32_t* __res
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_validate_centroids(const float* v, uint32_t nv, const uint32_t* f, uint32_t nt, int* cbox,
-                                     uint32_t* flags, hipStream_t s) {
-  k_init_cbox<<<1, 64, 0, s>>>(cbox, flags);
-  uint64_t work = nv > nt ? nv : nt;
-  uint32_t blocks = (uint32_t)((work + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
+hipError_t launch_vertex_pass(const float* v, uint32_t nv, int* vb, uint32_t* flags, hipStream_t s) {
+  k_init_vb<<<1, 64, 0, s>>>(vb, flags);
+  uint32_t blocks = (uint32_t)(((uint64_t)nv + kVpThreads - 1) / kVpThreads);
+  if (blocks > 2048) blocks = 2048;
   if (blocks == 0) blocks = 1;
-  k_validate_centroids<<<blocks, 256, 0, s>>>(v, nv, f, nt, cbox, flags);
+  k_vertex_pass<<<blocks, kVpThreads, 0, s>>>(v, nv, vb, flags);
   return hipGetLastError();
 }
 
-hipError_t launch_morton(const float* v, const uint32_t* f, uint32_t nt, const int* cbox, uint64_t* keys,
-                         uint32_t* vals, hipStream_t s) {
-  k_morton<<<(nt + 255) / 256, 256, 0, s>>>(v, f, nt, cbox, keys, vals);
+hipError_t launch_keys(const float* v, uint32_t nv, const uint32_t* f, uint32_t nt, const int* vb, uint64_t* keys,
+                       uint32_t* vals, uint32_t* flags, hipStream_t s) {
+  k_keys<<<(nt + 255) / 256, 256, 0, s>>>(v, nv, f, nt, vb, keys, vals, flags);
   return hipGetLastError();
 }
 

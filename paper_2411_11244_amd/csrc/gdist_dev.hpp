@@ -38,14 +38,32 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const
 }
 
 typedef float f2v __attribute__((ext_vector_type(2)));
+// Multi-dword global loads need only 4-byte alignment on this target, so a
+// 16-byte piece of a 24-byte box or a 36-byte triangle is one instruction.
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ T gload(const __attribute__((address_space(1))) float* p) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) T*>(p);
+}
+
 __device__ __forceinline__ Box load_box(const float* __restrict__ boxes, uint32_t node) {
-  const __attribute__((address_space(1))) f2v* p =
-      reinterpret_cast<const __attribute__((address_space(1))) f2v*>(gptr(boxes) + 6ull * node);
-  const f2v u = p[0], v = p[1], w = p[2];
+  const __attribute__((address_space(1))) float* p = gptr(boxes) + 6ull * node;
+  const f4u u = gload<f4u>(p);
+  const f2v w = gload<f2v>(p + 4);
   Box r;
-  r.lo[0] = u.x; r.lo[1] = u.y; r.lo[2] = v.x;
-  r.hi[0] = v.y; r.hi[1] = w.x; r.hi[2] = w.y;
+  r.lo[0] = u.x; r.lo[1] = u.y; r.lo[2] = u.z;
+  r.hi[0] = u.w; r.hi[1] = w.x; r.hi[2] = w.y;
   return r;
+}
+// The two sibling boxes of an even node id (48 bytes, 16-byte aligned).
+__device__ __forceinline__ void load_box_pair(const float* __restrict__ boxes, uint32_t even_node, Box* b) {
+  const __attribute__((address_space(1))) float* p = gptr(boxes) + 6ull * even_node;
+  const f4v u = gload<f4v>(p), v = gload<f4v>(p + 4), w = gload<f4v>(p + 8);
+  b[0].lo[0] = u.x; b[0].lo[1] = u.y; b[0].lo[2] = u.z;
+  b[0].hi[0] = u.w; b[0].hi[1] = v.x; b[0].hi[2] = v.y;
+  b[1].lo[0] = v.z; b[1].lo[1] = v.w; b[1].lo[2] = w.x;
+  b[1].hi[0] = w.y; b[1].hi[1] = w.z; b[1].hi[2] = w.w;
 }
 
 __device__ __forceinline__ void store_box(float* __restrict__ boxes, uint32_t node, const Box& b) {
@@ -82,8 +100,10 @@ __device__ __forceinline__ void xform(const Xf32& T, float x, float y, float z, 
 // Load triangle `pos` (9 floats, leaf order) and optionally transform it.
 __device__ __forceinline__ void load_tri(const float* __restrict__ tris, uint32_t pos, float* o) {
   const __attribute__((address_space(1))) float* p = gptr(tris) + 9ull * pos;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) o[k] = p[k];
+  const f4u u = gload<f4u>(p), v = gload<f4u>(p + 4);
+  o[0] = u.x; o[1] = u.y; o[2] = u.z; o[3] = u.w;
+  o[4] = v.x; o[5] = v.y; o[6] = v.z; o[7] = v.w;
+  o[8] = p[8];
 }
 __device__ __forceinline__ void load_tri_xf(const float* __restrict__ tris, uint32_t pos, const Xf32& T,
                                             float* o) {

@@ -37,6 +37,7 @@ struct Mesh {
   float* boxes = nullptr;
   uint32_t* fl = nullptr;   // deformable meshes: vertex indices of each triangle, leaf order
   float root[6] = {0, 0, 0, 0, 0, 0};
+  float rmax = 0.f;         // upper bound of the largest local vertex norm
   uint64_t bytes = 0;
 };
 
@@ -100,6 +101,14 @@ struct gdist_ctx {
   };
   std::unordered_map<WarmKey, std::pair<uint32_t, uint32_t>, WarmHash> warm;
   std::vector<gd::SlotState> warm_st;      // slot states copied back by the latest batch
+  // one-to-many calls: world-frame trees of the static meshes under the poses
+  // they were queried at (dropped when the mesh is released or updated)
+  struct WorldTree {
+    gdist_pose_t pose;
+    DevBuf boxes;
+  };
+  std::unordered_map<uint64_t, std::vector<WorldTree>> world;
+  uint32_t one_to_many = 1;                // 0: pairwise refits, 1: shared refit when it refits less, 2: shared
   unsigned long long last_ctl_sum[gd::ST_N] = {};
   gdist_stats_t last{};
   bool busy = false;                       // a server owns the stream and workspace

@@ -11,6 +11,9 @@ namespace gd {
 // Per-query description, written by the host once per query.
 // "A" is the tree kept static (its local frame is the query frame); "B" is
 // the tree refitted into A's frame.  `swapped` says the caller's mesh a is B.
+// One-to-many calls with a shared refit use the world as the query frame:
+// then A's tree was refitted into it under TA too, and the narrow phase
+// transforms A's triangles by TA (xfA = 1).
 struct SlotDesc {
   const float* boxA;    // [2 LA][6], A local frame
   const float* boxB;    // [2 LB][6], refitted into A's frame
@@ -28,7 +31,9 @@ struct SlotDesc {
   float kappa_u;        // delta = kappa_u * M
   float m_floor;        // least M: bounds the FP32 transform's rounding, which grows with
                         //   B's local coordinates and the translation, not with the query frame
-  Xf32 T;               // B local -> A local, FP32
+  Xf32 T;               // B local -> query frame (A local), FP32
+  Xf32 TA;              // A local -> query frame when xfA (else unused)
+  uint32_t xfA;
   double RA[9], tA[3];  // world pose of A, FP64
   double RB[9], tB[3];  // world pose of B, FP64
   double tau;           // tie tolerance (FP64)
@@ -143,10 +148,13 @@ struct StepHead {
 };
 
 // build.hip
-hipError_t launch_validate_centroids(const float* v, uint32_t nv, const uint32_t* f, uint32_t nt, int* cbox,
-                                     uint32_t* flags, hipStream_t s);
-hipError_t launch_morton(const float* v, const uint32_t* f, uint32_t nt, const int* cbox, uint64_t* keys,
-                         uint32_t* vals, hipStream_t s);
+// vb: 7 ints (vertex box as ordered floats, largest vertex norm); flags bit 1 =
+// a non-finite vertex.
+hipError_t launch_vertex_pass(const float* v, uint32_t nv, int* vb, uint32_t* flags, hipStream_t s);
+// keys/vals of every triangle (Morton code in the vertex box, iota); flags bit
+// 0 = a vertex index >= nv.  Needs vb from launch_vertex_pass.
+hipError_t launch_keys(const float* v, uint32_t nv, const uint32_t* f, uint32_t nt, const int* vb, uint64_t* keys,
+                       uint32_t* vals, uint32_t* flags, hipStream_t s);
 size_t radix_hist_words(uint32_t n);
 hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, uint32_t n,
                              uint32_t* hist, hipStream_t s, int* result_in_tmp);
@@ -188,6 +196,8 @@ hipError_t launch_reeval(const TravParams& p, hipStream_t s);
 hipError_t launch_reset(const TravParams& p, hipStream_t s);
 hipError_t launch_admit(const TravParams& p, hipStream_t s);
 hipError_t launch_slot_hist(const TravParams& p, uint32_t* live, hipStream_t s);
+static_assert(sizeof(SlotDesc) % 4 == 0, "descriptors are copied in 4-byte words");
+hipError_t launch_put_desc(const SlotDesc* stage, const uint32_t* list, uint32_t n, SlotDesc* desc, hipStream_t s);
 // The part of a serving step after its traversal launch: report head and
 // round advance, per-slot live counts, completion flags, FP64 re-evaluation
 // of the slots that completed (results in p.res).  Every launch has a fixed

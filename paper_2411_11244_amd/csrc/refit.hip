@@ -16,35 +16,64 @@
 namespace gd {
 
 constexpr int kRefitThreads = 512;
+constexpr uint32_t kStageFloats = 18u * kRefitThreads;   // at most two triangles per leaf
+
+// Box of leaf blk * S + threadIdx.x (threads >= S: an empty box) of a tree
+// with n triangles and L = 2^D leaves under transform T.  The workgroup's S
+// leaves hold one contiguous run of at most 2S triangles; it is read with
+// 16-byte loads across the whole workgroup (each wave reads 1 KB of
+// consecutive bytes per instruction) into LDS, and every thread then
+// transforms its leaf's one or two triangles from there, with the same fused
+// multiply-add order as the narrow phase.
+__device__ __forceinline__ Box staged_leaf_box(const float* __restrict__ tris, uint32_t n, uint32_t L, const Xf32& T,
+                                               uint32_t blk, uint32_t S, float* __restrict__ stage) {
+  const uint32_t D = 31u - (uint32_t)__clz(L);
+  const uint32_t t0 = (uint32_t)(((uint64_t)blk * S * n) >> D);
+  const uint32_t t1 = (uint32_t)(((uint64_t)(blk * S + S) * n) >> D);
+  const uint32_t nf = 9u * (t1 - t0);
+  const __attribute__((address_space(1))) float* src = gptr(tris) + 9ull * t0;
+  const uint32_t n4 = nf >> 2;
+  for (uint32_t i = threadIdx.x; i < n4; i += blockDim.x)
+    *reinterpret_cast<f4v*>(stage + 4u * i) = gload<f4u>(src + 4u * i);
+  for (uint32_t i = 4u * n4 + threadIdx.x; i < nf; i += blockDim.x) stage[i] = src[i];
+  __syncthreads();
+  Box b;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    b.lo[k] = __builtin_huge_valf();
+    b.hi[k] = -__builtin_huge_valf();
+  }
+  const uint32_t j = threadIdx.x;
+  if (j < S) {
+    const uint32_t leaf = blk * S + j;
+    const uint32_t start = (uint32_t)(((uint64_t)leaf * n) >> D);
+    const uint32_t end = (uint32_t)(((uint64_t)(leaf + 1) * n) >> D);
+    for (uint32_t p = start; p < end; ++p) {
+      const float* q = stage + 9u * (p - t0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float w[3];
+        xform(T, q[3 * c], q[3 * c + 1], q[3 * c + 2], w);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          b.lo[k] = fminf(b.lo[k], w[k]);
+          b.hi[k] = fmaxf(b.hi[k], w[k]);
+        }
+      }
+    }
+  }
+  return b;
+}
 
 __global__ __launch_bounds__(kRefitThreads) void k_refit_leaves(const float* __restrict__ tris, uint32_t n,
                                                                  uint32_t L, Xf32 T, float* __restrict__ boxes,
                                                                  uint32_t S) {
   __shared__ Box lb[kRefitThreads];
+  __shared__ __align__(16) float stage[kStageFloats];
   const uint32_t j = threadIdx.x;
-  Box b;
+  const Box b = staged_leaf_box(tris, n, L, T, blockIdx.x, S, stage);
   if (j < S) {
-    uint32_t leaf = blockIdx.x * S + j;
-    const uint32_t D = 31u - (uint32_t)__clz(L);   // L = 2^D
-    uint32_t start = (uint32_t)(((uint64_t)leaf * n) >> D);
-    uint32_t end = (uint32_t)(((uint64_t)(leaf + 1) * n) >> D);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      b.lo[k] = __builtin_huge_valf();
-      b.hi[k] = -__builtin_huge_valf();
-    }
-    for (uint32_t p = start; p < end; ++p) {
-      float t[9];
-      load_tri_xf(tris, p, T, t);
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          b.lo[k] = fminf(b.lo[k], t[3 * c + k]);
-          b.hi[k] = fmaxf(b.hi[k], t[3 * c + k]);
-        }
-    }
-    store_box(boxes, L + leaf, b);
+    store_box(boxes, L + blockIdx.x * S + j, b);
     lb[j] = b;
   }
   uint32_t base = L + blockIdx.x * S;
@@ -106,34 +135,15 @@ __device__ __forceinline__ const J* find_job(const J* jobs, uint32_t njobs) {
 __global__ __launch_bounds__(kRefitThreads) void k_refit_leaves_batch(const RefitJob* __restrict__ jobs,
                                                                        uint32_t njobs) {
   __shared__ Box lb[kRefitThreads];
+  __shared__ __align__(16) float stage[kStageFloats];
   const RefitJob* jp = find_job(jobs, njobs);
   const RefitJob J = *jp;
   const uint32_t j = threadIdx.x;
   const uint32_t blk = blockIdx.x - J.first_block;
-  const uint32_t S = J.S, L = J.L, n = J.n;
+  const uint32_t S = J.S, L = J.L;
+  const Box b = staged_leaf_box(J.tris, J.n, L, J.T, blk, S, stage);
   if (j < S) {
-    Box b;
-    uint32_t leaf = blk * S + j;
-    const uint32_t D = 31u - (uint32_t)__clz(L);
-    uint32_t start = (uint32_t)(((uint64_t)leaf * n) >> D);
-    uint32_t end = (uint32_t)(((uint64_t)(leaf + 1) * n) >> D);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      b.lo[k] = __builtin_huge_valf();
-      b.hi[k] = -__builtin_huge_valf();
-    }
-    for (uint32_t p = start; p < end; ++p) {
-      float t[9];
-      load_tri_xf(J.tris, p, J.T, t);
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          b.lo[k] = fminf(b.lo[k], t[3 * c + k]);
-          b.hi[k] = fmaxf(b.hi[k], t[3 * c + k]);
-        }
-    }
-    store_box(J.boxes, L + leaf, b);
+    store_box(J.boxes, L + blk * S + j, b);
     lb[j] = b;
   }
   uint32_t base = L + blk * S;

@@ -66,6 +66,7 @@ struct gdist_server {
   size_t box_stride = 0;  // floats of refitted boxes per slot
   uint32_t max_leaves = 0;
   DevBuf desc, st, boxes, front[2], leaf[2], stack, counts, cand, cand64, ctl, list, tab;
+  DevBuf desc_stage;          // the descriptors admitted by a step, in list order
   DevBuf rep;                 // step report: StepHead, live[S], finish[S], results[S]
   size_t live_off = 0, fin_off = 0, res_off = 0, rep_bytes = 0;
   void* rep_host = nullptr;   // pinned copy of the report
@@ -297,11 +298,14 @@ gdist_status_t admit(gdist_server* sv, std::vector<Pending>& reqs) {
     slots.push_back(slot);
   }
   if (slots.empty()) return GDIST_OK;
-  for (size_t i = 0; i < slots.size(); ++i)
-    HIPCHK(hipMemcpyAsync((SlotDesc*)sv->desc.p + slots[i], stage + desc_off + sizeof(SlotDesc) * i, sizeof(SlotDesc),
-                          hipMemcpyHostToDevice, c->stream));
+  // one copy of the new descriptors (list order) and of the slot list, then
+  // a kernel puts each descriptor in its slot
+  HIPCHK(hipMemcpyAsync(sv->desc_stage.p, stage + desc_off, sizeof(SlotDesc) * slots.size(), hipMemcpyHostToDevice,
+                        c->stream));
   std::memcpy(stage + list_off, slots.data(), 4 * slots.size());
   HIPCHK(hipMemcpyAsync(sv->list.p, stage + list_off, 4 * slots.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(launch_put_desc((const SlotDesc*)sv->desc_stage.p, (const uint32_t*)sv->list.p, (uint32_t)slots.size(),
+                         (SlotDesc*)sv->desc.p, c->stream));
   RefitPlan plan;
   const size_t cap = sv->pinned_bytes - tab_off;
   const size_t bytes = plan_refit_batch(jobs.data(), (uint32_t)jobs.size(), stage + tab_off, cap, &plan);
@@ -459,7 +463,7 @@ void worker_main(gdist_server* sv) {
 void free_server(gdist_server* sv) {
   gdist_ctx* c = sv->c;
   drop_graph(sv);
-  DevBuf* bufs[] = {&sv->desc,  &sv->st,     &sv->rep,    &sv->boxes, &sv->front[0], &sv->front[1],
+  DevBuf* bufs[] = {&sv->desc,  &sv->desc_stage, &sv->st, &sv->rep, &sv->boxes, &sv->front[0], &sv->front[1],
                     &sv->leaf[0], &sv->leaf[1], &sv->stack, &sv->counts, &sv->cand,    &sv->cand64,
                     &sv->ctl,   &sv->list,   &sv->tab};
   for (DevBuf* b : bufs) release_buf(c, *b);
@@ -518,6 +522,7 @@ gdist_status_t gdist_server_start(gdist_ctx_t c, const gdist_server_config_t* co
   sv->res_off = (sv->fin_off + 4ull * sv->S + 255) & ~(size_t)255;
   sv->rep_bytes = sv->res_off + sizeof(gdist_result_t) * sv->S;
   A(sv->desc, sizeof(SlotDesc) * sv->S);
+  A(sv->desc_stage, sizeof(SlotDesc) * sv->S);
   A(sv->st, sizeof(SlotState) * sv->S);
   A(sv->rep, sv->rep_bytes);
   A(sv->boxes, sizeof(float) * sv->box_stride * sv->S);

@@ -47,8 +47,10 @@ constexpr int kWavesPerBlock = kTravThreads / kWave;
 constexpr int kTravBlock = 1024;                  // k_traverse: one 16-wave workgroup per CU
 constexpr int kTravWaves = kTravBlock / kWave;
 constexpr uint32_t kQueue = 320;  // per-wave LDS queue of triangle pairs (63 + 4 x 64)
-constexpr int kRows = 8;          // expansion rows per wave iteration
+constexpr int kRows = 8;          // expansion rows per wave iteration (one lane per child pair)
+constexpr int kEntRows = 1;       // k = 1 rounds: rows of input entries per wave iteration (4 children each)
 static_assert(kTravWaves * kRows * 64 + 256 <= (int)kSegSlack, "segment slack below one task group per wave");
+static_assert(kEntRows * 4 <= kRows, "a k = 1 task appends no more than a child-pair task");
 
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -179,9 +181,16 @@ __device__ __forceinline__ void leaf_range(uint32_t node, uint32_t D, uint32_t n
   e = (uint32_t)(((uint64_t)(j + 1) * n) >> D);
 }
 
+// A's triangle `pos` in the query frame: A's local frame, or transformed by
+// TA when A's tree was refitted too (one-to-many calls in the world frame).
+__device__ __forceinline__ void load_tri_a(const float* trisA, bool xfA, const Xf32& TA, uint32_t pos, float* o) {
+  if (xfA) load_tri_xf(trisA, pos, TA, o);
+  else load_tri(trisA, pos, o);
+}
+
 __device__ __forceinline__ void load_pair(const SlotDesc* d, uint32_t pa, uint32_t pb, V3<float>* P, V3<float>* Q) {
   float a[9], b[9];
-  load_tri(d->trisA, pa, a);
+  load_tri_a(d->trisA, d->xfA != 0u, d->TA, pa, a);
   load_tri_xf(d->trisB, pb, d->T, b);
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
@@ -450,7 +459,7 @@ struct SlotView {
   const float* boxB;
   const float* trisA;
   const float* trisB;
-  uint32_t mode, depthA, depthB, LA, LB, nA, nB, enh;
+  uint32_t mode, depthA, depthB, LA, LB, nA, nB, enh, xfA;
   float delta, best;
 };
 __device__ __forceinline__ void fill_view(const TravParams& p, const BlockState* bs, bool lds, uint32_t slot,
@@ -468,6 +477,7 @@ __device__ __forceinline__ void fill_view(const TravParams& p, const BlockState*
   v.nA = d.nA;
   v.nB = d.nB;
   v.enh = d.enhanced;
+  v.xfA = d.xfA;
   v.delta = get_delta(p, bs, lds, slot);
   v.best = get_best(p, bs, lds, slot);
 }
@@ -536,6 +546,35 @@ __device__ __forceinline__ void append_rows(const bool* take, const uint4* e, ui
       if (idx < seg) out[idx] = e[r];
     }
     base += (uint32_t)__popcll(m[r]);
+  }
+}
+
+// Append up to four entries per lane (those with take[j] set) to this
+// workgroup's segment of `buf`, lane after lane, each lane's entries
+// contiguous and in order, with one LDS atomic: the children of one parent
+// stay adjacent, as in the one-lane-per-child-pair order, so the next round
+// reads neighbouring boxes and triangles from neighbouring lanes.
+__device__ __forceinline__ void append_runs4(const bool* take, const uint4* e, uint4* buf, uint32_t seg,
+                                             uint32_t* lds_count, uint32_t* overflow, uint32_t ovf_bit, uint32_t lane,
+                                             uint64_t lt) {
+  const uint32_t cnt = (uint32_t)take[0] + (uint32_t)take[1] + (uint32_t)take[2] + (uint32_t)take[3];
+  const uint64_t b0 = __ballot(cnt & 1u), b1 = __ballot(cnt & 2u), b2 = __ballot(cnt & 4u);
+  const uint32_t tot = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) + 4u * (uint32_t)__popcll(b2);
+  if (tot == 0u) return;
+  uint32_t base = 0;
+  if (lane == 0) {
+    base = atomicAdd(lds_count, tot);
+    if (base + tot > seg) atomicOr(overflow, ovf_bit);
+  }
+  base = lane_value(base, 0);
+  uint32_t idx = base + (uint32_t)__popcll(b0 & lt) + 2u * (uint32_t)__popcll(b1 & lt) + 4u * (uint32_t)__popcll(b2 & lt);
+  uint4* out = buf + (uint64_t)blockIdx.x * seg;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (take[j]) {
+      if (idx < seg) out[idx] = e[j];
+      ++idx;
+    }
   }
 }
 
@@ -618,6 +657,132 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
   append_rows<R>(to_front, ne, rd.fout, rd.seg_f, &bs->fo, &c->overflow, 1u, lane, lt);
 }
 
+// One child pair of an expanded entry: cull bound, improving bound, output
+// entry.  Boxes ba (of A) and bb (of B); `valid` lanes only.
+struct ChildOut {
+  bool leaf, front;
+  uint4 e;
+};
+__device__ __forceinline__ void eval_child(const SlotView& v, bool valid, const Box& ba, const Box& bb, uint32_t ca,
+                                           uint32_t cb, uint32_t slot, ChildOut& o, float& imp) {
+  bool keep = false;
+  float nkey = 0.f;
+  if (valid) {
+    const bool enh = v.enh != 0;
+    if (v.mode == 0) {
+      nkey = min_lower(ba, bb);
+      keep = nkey - v.delta <= v.best;
+      imp = fminf(imp, min_upper(ba, bb, enh) + v.delta);
+    } else {
+      nkey = max_upper(ba, bb);
+      keep = nkey + v.delta >= v.best;
+      imp = fmaxf(imp, fmaxf(max_lower(ba, bb, enh) - v.delta, 0.f));
+    }
+  }
+  const bool isleaf = (ca >= v.LA) && (cb >= v.LB);
+  o.e = make_uint4(ca, cb, fbits(nkey), slot);
+  o.leaf = keep && isleaf;
+  o.front = keep && !isleaf;
+}
+
+// Expansion in rounds with k = 1, one lane per input entry (items it0 + 64 r
+// + lane are input entries here, not child pairs).  The lane reads its entry
+// once and the boxes of its children from registers-sized sibling groups,
+// then evaluates its (up to) four child pairs: a quarter of the entry loads
+// and about half the box loads of one lane per child pair.
+//
+// The two levels of a round are shared as in the child-pair mapping: one per
+// side, or both to one side when the other is at its leaf level.  Call G the
+// side that descends further (kG = max(kA, kB), 1 or 2) and S the other
+// (kS = 0 or 1): the lane loads G's 2^kG children (one or two sibling pairs,
+// 48 bytes each, three 16-byte loads per pair) and S's sibling pair holding
+// its 2^kS children (for kS = 0, the pair holding S's own node).  The bounds
+// are symmetric in their two boxes (bit for bit: A's and B's per-axis terms
+// swap places in commutative sums, minima and maxima), so every child pair is
+// evaluated as (G box, S box) whichever side G is, with no branch on the
+// split: lanes of one wave may split differently.
+template <int R>
+__device__ __forceinline__ void expand_entries(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base0,
+                                               uint32_t n_ent, uint32_t lane, uint64_t lt, WaveStats& ws,
+                                               LaneStats& ls) {
+  Ctl* c = p.ctl;
+  uint4 ent[R];
+  bool act[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t rb = base0 + 64u * r;
+    const uint32_t ei = rb + lane;
+    act[r] = ei < n_ent;
+    ent[r] = make_uint4(1u, 1u, 0u, 0u);
+    if (rb < n_ent) {
+      const uint32_t elast = n_ent - 1u < rb + 63u ? n_ent - 1u : rb + 63u;
+      if (rb < rd.n_in) {
+        const uint32_t fend = elast < rd.n_in ? elast : rd.n_in - 1u;
+        const uint32_t addr = row_addr(bs->fpre, rd.nb, rd.seg_f, rb, fend, ei < rd.n_in ? ei : fend, lane);
+        if (act[r]) ent[r] = ei < rd.n_in ? rd.fin[addr] : rd.stk[(uint64_t)rd.pop_base + (ei - rd.n_in)];
+      } else if (act[r]) {
+        ent[r] = rd.stk[(uint64_t)rd.pop_base + (ei - rd.n_in)];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t x = ent[r].x, y = ent[r].y, slot = ent[r].w;
+    const SlotView v = slot_view(p, bs, rd.lds_slots, act[r], slot);
+    const uint32_t mode = v.mode;
+    const float key = bitsf(ent[r].z);
+    const bool a = act[r] && (mode == 0 ? !(key - v.delta > v.best) : !(key + v.delta < v.best));
+    uint32_t kA, kB;
+    split_levels(v.depthA - level_of(x), v.depthB - level_of(y), 2u, kA, kB);
+    const bool gA = kA >= kB;                 // G = A (else B)
+    const uint32_t kG = gA ? kA : kB, kS = gA ? kB : kA;
+    const bool quad = kG == 2u;
+    const uint32_t g = gA ? x : y, sn = gA ? y : x;
+    const float* gbox = gA ? v.boxA : v.boxB;
+    const float* sbox = gA ? v.boxB : v.boxA;
+    const uint32_t gfirst = (g << kG) & ~1u;                // G's first child (kG >= 1: even)
+    const uint32_t spair = (sn << kS) & ~1u;                // S's sibling pair
+    Box G[4], S2[2];
+    if (a) {
+      load_box_pair(gbox, gfirst, G);
+      load_box_pair(sbox, spair, S2);
+    }
+    if (a && quad) load_box_pair(gbox, gfirst + 2u, G + 2);
+    add_stat(ws, ST_POPPED, a);
+    ls.boxes += a ? (1u << kA) + (1u << kB) : 0u;
+    // S's own node when it stays at its level
+    if (kS == 0u && (sn & 1u)) S2[0] = S2[1];
+    bool tl[4], tf[4];
+    uint4 ne[4];
+    float imp = mode == 0 ? __builtin_huge_valf() : 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      // child j: G child gi, S child si (quad: G's four children against S)
+      const uint32_t gi = quad ? (uint32_t)j : ((uint32_t)j & 1u);
+      const uint32_t si = quad ? 0u : ((uint32_t)j >> 1);
+      const bool valid = a && (quad || si <= kS);
+      Box gb = G[j & 1], sb = S2[0];
+      if (j >= 2) {
+        if (quad) gb = G[j];
+        else sb = S2[1];
+      }
+      const uint32_t gc = gfirst | gi, sc = (sn << kS) | si;
+      const uint32_t ca = gA ? gc : sc, cb = gA ? sc : gc;
+      ChildOut o;
+      eval_child(v, valid, gb, sb, ca, cb, slot, o, imp);
+      add_stat(ws, ST_CHILD, valid);
+      add_stat(ws, ST_PUSHED, o.leaf || o.front);
+      tl[j] = o.leaf;
+      tf[j] = o.front;
+      ne[j] = o.e;
+    }
+    const bool helps = a && (mode == 0 ? imp < v.best : imp > v.best);
+    improve_best(p, bs, rd.lds_slots, helps, slot, mode, imp, lane);
+    append_runs4(tl, ne, rd.lout, rd.seg_l, &bs->lo, &c->overflow, 2u, lane, lt);
+    append_runs4(tf, ne, rd.fout, rd.seg_f, &bs->fo, &c->overflow, 1u, lane, lt);
+  }
+}
+
 // Move front entries [n_in + base, n_in + base + 64) onto the spill stack
 // (one lane per entry).
 __device__ __forceinline__ void spill_wave(const BlockState* bs, const Round& rd, uint32_t base, uint32_t lane) {
@@ -628,10 +793,9 @@ __device__ __forceinline__ void spill_wave(const BlockState* bs, const Round& rd
   if (j < rd.n_spill) rd.stk[(uint64_t)rd.st + j] = rd.fin[addr];
 }
 
-// Append a candidate triangle pair (d32 within the window of the slot's
-// bound) to the slot's region; rare, so one atomic per candidate.
-__device__ __forceinline__ void add_candidate(const TravParams& p, uint32_t slot, uint32_t pa, uint32_t pb, float dd) {
-  uint32_t idx = atomicAdd(&p.st[slot].n_cand, 1u);
+// Place candidate number idx of a slot (or flag the slot's region as full).
+__device__ __forceinline__ void put_candidate(const TravParams& p, uint32_t slot, uint32_t idx, uint32_t pa,
+                                              uint32_t pb, float dd) {
   if (idx < p.cand_per_slot) {
     Cand ce;
     ce.d32 = dd;
@@ -642,6 +806,25 @@ __device__ __forceinline__ void add_candidate(const TravParams& p, uint32_t slot
   } else {
     atomicOr(&p.st[slot].cand_overflow, 1u);
     if (p.cand_stop) atomicOr(&p.ctl->overflow, 4u);
+  }
+}
+// Append the flagged lanes' candidates (d32 within the window of their slot's
+// bound) to their slots' regions.  When all of them belong to one slot (the
+// usual case) the wave takes their places with one atomic, else each lane
+// with its own.  Needs the whole wave.
+__device__ __forceinline__ void add_candidates(const TravParams& p, bool cand, uint32_t slot, uint32_t pa,
+                                               uint32_t pb, float dd, uint32_t lane, uint64_t lt) {
+  const uint64_t m = __ballot(cand);
+  if (m == 0ull) return;
+  const uint32_t fl = first_lane(m);
+  const uint32_t s0 = lane_value(slot, fl);
+  if (__ballot(cand && slot != s0) == 0ull) {
+    uint32_t base = 0u;
+    if (lane == fl) base = atomicAdd(&p.st[s0].n_cand, (uint32_t)__popcll(m));
+    base = lane_value(base, fl);
+    if (cand) put_candidate(p, s0, base + (uint32_t)__popcll(m & lt), pa, pb, dd);
+  } else if (cand) {
+    put_candidate(p, slot, atomicAdd(&p.st[slot].n_cand, 1u), pa, pb, dd);
   }
 }
 
@@ -692,7 +875,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
       float a[9], b[9];
       const uint32_t ia = sa + i < ea ? sa + i : sa;
       const uint32_t ib = sb + i < eb ? sb + i : sb;
-      load_tri(v.trisA, ia, a);
+      load_tri_a(v.trisA, v.xfA != 0u, p.desc[slot].TA, ia, a);
       load_tri_xf(v.trisB, ib, T, b);
 #pragma unroll
       for (int w = 0; w < 3; ++w) {
@@ -719,7 +902,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
         imp = fmaxf(imp, fmaxf(dd - delta, 0.f));
         cand = dd + delta >= best;
       }
-      if (cand) add_candidate(p, slot, pa, pb, dd);
+      add_candidates(p, cand, slot, pa, pb, dd, lane, lt);
       add_stat(ws, ST_FULL, full);
       add_stat(ws, ST_CAND, cand);
     }
@@ -745,7 +928,7 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
     V3<float> P[3], Q[3];
     {
       float a[9], b[9];
-      load_tri(v.trisA, pa, a);
+      load_tri_a(v.trisA, v.xfA != 0u, p.desc[slot].TA, pa, a);
       load_tri_xf(v.trisB, pb, p.desc[slot].T, b);
 #pragma unroll
       for (int w = 0; w < 3; ++w) {
@@ -765,7 +948,7 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
     }
   }
   add_stat(ws, ST_FULL, act);
-  if (act && cand) add_candidate(p, slot, pa, pb, dd);
+  add_candidates(p, act && cand, slot, pa, pb, dd, lane, lt);
   add_stat(ws, ST_CAND, act && cand);
   improve_best(p, bs, lds, act, slot, mode, improve, lane);
   improve_bound(&p.st[0].best32, sizeof(SlotState) / 4, act, slot, mode, dd, lane);
@@ -872,9 +1055,12 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     const uint32_t kk = 2u * k;
     const uint32_t leaf_waves = (nl + 63u) >> 6;   // one lane per leaf pair
     const uint32_t spill_end = leaf_waves + ((rd.n_spill + 63u) >> 6);
-    const uint32_t exp_items = n_exp << kk;
-    // expansion work is handed out in groups of kRows waves' worth of items
-    const uint32_t total = spill_end + (uint32_t)(((uint64_t)exp_items + 64u * kRows - 1u) / (64u * kRows));
+    // k = 1: one lane per input entry, else one lane per child pair
+    const bool by_entry = kk == 2u;
+    const uint32_t exp_items = by_entry ? n_exp : n_exp << kk;
+    const uint32_t rows = by_entry ? (uint32_t)kEntRows : (uint32_t)kRows;
+    // expansion work is handed out in groups of `rows` waves' worth of items
+    const uint32_t total = spill_end + (uint32_t)(((uint64_t)exp_items + 64u * rows - 1u) / (64u * rows));
     uint32_t qn = 0;  // wave-uniform fill of this wave's LDS queue
     // a leaf task's entries are loaded one task ahead, so their latency
     // overlaps the previous task's triangle loads
@@ -887,6 +1073,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
           if (w + nw < leaf_waves) lent = leaf_row(bs, rd, (w + nw) * 64u, nl, lane);
           narrow_filter_wave(p, bs, rd, w * 64u, nl, cur, lane, lt, q, qn, ws, ls);
         } else if (w < spill_end) spill_wave(bs, rd, (w - leaf_waves) * 64u, lane);
+        else if (by_entry) expand_entries<kEntRows>(p, bs, rd, (w - spill_end) * 64u * kEntRows, exp_items, lane, lt, ws, ls);
         else expand_rows<kRows>(p, bs, rd, (w - spill_end) * 64u * kRows, exp_items, kk, lane, lt, ws, ls);
         w += nw;
       }
@@ -1137,6 +1324,23 @@ uint32_t reeval_groups(uint32_t n_list) {
   return g < 1u ? 1u : (g > 64u ? 64u : g);
 }
 
+// Serving admission: descriptor i of a staged block goes to slot list[i]
+// (one workgroup per descriptor), so a step's new descriptors need one copy.
+__global__ void k_put_desc(const SlotDesc* __restrict__ stage, const uint32_t* __restrict__ list, uint32_t n,
+                           SlotDesc* __restrict__ desc) {
+  const uint32_t i = blockIdx.x;
+  if (i >= n) return;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(stage + i);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(desc + list[i]);
+  for (uint32_t w = threadIdx.x; w < sizeof(SlotDesc) / 4; w += blockDim.x) dst[w] = src[w];
+}
+
+hipError_t launch_put_desc(const SlotDesc* stage, const uint32_t* list, uint32_t n, SlotDesc* desc, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_put_desc<<<n, 64, 0, s>>>(stage, list, n, desc);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset(const TravParams& p, hipStream_t s) {
   k_reset<<<1, 256, 0, s>>>(p);
   return hipGetLastError();
@@ -1166,6 +1370,13 @@ hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, u
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) return e;
   uint32_t b = (uint32_t)per_cu;
+  // Every workgroup must be resident at once (grid barrier).  The occupancy
+  // count assumes a workgroup's waves spread evenly over a CU's four SIMDs;
+  // a workgroup whose wave count is not a multiple of four puts one more wave
+  // on some SIMDs, so two of them can need more registers on one SIMD than it
+  // has although the count says they fit.  Only then is the grid held to one
+  // workgroup per CU.
+  if ((kTravBlock / kWave) % 4 != 0 && b > 1u) b = 1u;
   if (blocks_per_cu > 0 && blocks_per_cu < b) b = blocks_per_cu;
   if (b == 0) b = 1;
   uint32_t total = b * (uint32_t)prop.multiProcessorCount;

@@ -67,7 +67,8 @@ class gdist_stats_t(C.Structure):
         "tri_full", "candidates", "front_peak", "bytes_refit", "bytes_traversal", "bytes_narrow", "retries")] + \
                [("ms_refit", C.c_double), ("ms_traversal", C.c_double), ("ms_total", C.c_double),
                 ("ms_traverse_kernel", C.c_double), ("traverse_launches", C.c_uint64),
-                ("child_boxes", C.c_uint64), ("leaf_tris", C.c_uint64), ("bytes_reeval", C.c_uint64)]
+                ("child_boxes", C.c_uint64), ("leaf_tris", C.c_uint64), ("bytes_reeval", C.c_uint64),
+                ("refit_trees", C.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

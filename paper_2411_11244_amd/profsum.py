@@ -2,6 +2,7 @@
 
     python -m paper_2411_11244_amd.profsum stats  <kernel_stats.csv> <bench log> "<command>" "<title>"
     python -m paper_2411_11244_amd.profsum pmc    <fetch counter csv> <write counter csv> "<commands>" "<title>" <calibration bytes>
+    python -m paper_2411_11244_amd.profsum counters "<commands>" "<title>" <counter csv> [<counter csv> ...]
 
 ``stats`` turns a ``--kernel-trace --stats`` kernel table into a markdown
 table and appends the bench.py line the same run printed.
@@ -79,6 +80,40 @@ def pmc(fetch_csv: str, write_csv: str, cmds: str, title: str, calib_bytes: int)
     return "\n".join(out)
 
 
+def counters(csvs, cmds: str, title: str) -> str:
+    """Per-dispatch means of every counter in one or more ``--pmc`` runs, for
+    the traversal kernel, with the derived utilisations computed from them."""
+    vals = {}
+    for path in csvs:
+        per = defaultdict(lambda: defaultdict(float))   # counter -> dispatch -> value
+        names = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                d = r["Dispatch_Id"]
+                names[d] = r["Kernel_Name"]
+                per[r["Counter_Name"]][d] += float(r["Counter_Value"])
+        for cn, byd in per.items():
+            tv = [v for d, v in byd.items() if TRAVERSE in names[d]]
+            if tv:
+                vals[cn] = (sum(tv) / len(tv), len(tv))
+    out = [f"# {title}", "", "Commands (run from the repository root on one MI355X):", "", "```", cmds, "```", "",
+           "| counter | mean per k_traverse dispatch | dispatches |", "|---|---|---|"]
+    for cn in sorted(vals):
+        out.append(f"| {cn} | {vals[cn][0]:.6g} | {vals[cn][1]} |")
+    der = []
+    v = {k: x[0] for k, x in vals.items()}
+    if "SQ_INSTS_VALU" in v and "SQ_WAVES" in v:
+        der.append(("VALU instructions per wave", v["SQ_INSTS_VALU"] / max(1.0, v["SQ_WAVES"])))
+    if "TCC_HIT_sum" in v and "TCC_MISS_sum" in v:
+        der.append(("L2 hit rate", v["TCC_HIT_sum"] / max(1.0, v["TCC_HIT_sum"] + v["TCC_MISS_sum"])))
+    if "TCP_TCC_READ_REQ_sum" in v and "TCP_TOTAL_CACHE_ACCESSES_sum" in v:
+        der.append(("L1 hit rate (1 - L1-to-L2 reads / L1 accesses)",
+                    1.0 - v["TCP_TCC_READ_REQ_sum"] / max(1.0, v["TCP_TOTAL_CACHE_ACCESSES_sum"])))
+    if der:
+        out += ["", "| derived | value |", "|---|---|"] + [f"| {k} | {x:.4g} |" for k, x in der]
+    return "\n".join(out)
+
+
 def read_record(path: str):
     """The PMC_RECORD of a summary, or None."""
     try:
@@ -113,6 +148,9 @@ def main(argv=None) -> int:
     a = sys.argv[1:] if argv is None else argv
     if len(a) >= 5 and a[0] == "stats":
         print(stats(a[1], a[2], a[3], a[4]))
+        return 0
+    if len(a) >= 4 and a[0] == "counters":
+        print(counters(a[3:], a[1], a[2]))
         return 0
     if len(a) >= 6 and a[0] == "pmc":
         print(pmc(a[1], a[2], a[3], a[4], int(a[5])))

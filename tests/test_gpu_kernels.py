@@ -59,11 +59,11 @@ def test_tri_tri_vs_oracle(orc, gctx, mode):
 
 def numpy_morton_order(mesh):
     """Leaf order from the definition: 21-bit-per-axis Morton code of the FP32
-    centroid in the centroid box, stable sort."""
+    centroid in the box of all vertices, stable sort."""
     v = mesh.verts
     t = mesh.tris
     c = (v[t[:, 0]] + v[t[:, 1]] + v[t[:, 2]]) * np.float32(1.0 / 3.0)
-    lo, hi = c.min(0), c.max(0)
+    lo, hi = v.min(0), v.max(0)
     ext = hi - lo
     u = np.where(ext > 0, (c - lo) / np.where(ext > 0, ext, 1), 0).astype(np.float32)
     s = u * np.float32(2097152.0)

@@ -443,3 +443,52 @@ def test_one_to_many_equals_single(orc, gctx):
         gdist.gdist_release(gctx, ha)
         for h in hbs:
             gdist.gdist_release(gctx, h)
+
+
+def test_one_to_many_shared_refit(orc, gctx):
+    """One moving mesh against 64 resident meshes at fixed world poses: with the
+    shared refit, a call refits the moving mesh once (the static meshes' world
+    trees are kept from the first call), and every result equals the query
+    alone and the pairwise plan; a sample matches the oracle.  Updating or
+    releasing a static mesh drops its kept trees."""
+    rng = np.random.default_rng(67)
+    A = g.random_mesh_of_size(rng, 20000)
+    statics = [g.random_mesh_of_size(rng, int(t)) for t in rng.integers(500, 4000, 64)]
+    ha = build(gctx, A)
+    hbs = [build(gctx, m) for m in statics]
+    try:
+        base_pa = (g.random_rotation(rng), np.zeros(3))
+        poses = [g.place_with_gap(rng, A, m, float(gap), base_pa[0], g.random_rotation(rng))[1]
+                 for m, gap in zip(statics, rng.choice([0.01, 0.2, -0.05], 64))]
+        for mode in (0, 1):
+            gdist.gdist_set_option(gctx, "one_to_many", 2)
+            for call in range(3):
+                # the moving mesh turns and shifts a little from call to call
+                pa = (g.random_rotation(rng) if call else base_pa[0], rng.normal(size=3) * 0.01 * call)
+                res = gdist.gdist_query_one_to_many(gctx, ha, pa, hbs, poses, mode)
+                st = gdist.gdist_last_stats(gctx)
+                assert st["refit_trees"] == (1 if (call or mode) else 65), st["refit_trees"]
+                gdist.gdist_set_option(gctx, "one_to_many", 0)
+                pw = gdist.gdist_query_one_to_many(gctx, ha, pa, hbs, poses, mode)
+                assert gdist.gdist_last_stats(gctx)["refit_trees"] == 64
+                gdist.gdist_set_option(gctx, "one_to_many", 2)
+                for i, (r, q) in enumerate(zip(res, pw)):
+                    assert r["distance"] == q["distance"], (i, r["distance"], q["distance"])
+                    assert (r["tri_a"], r["tri_b"]) == (q["tri_a"], q["tri_b"]) and r["n_ties"] == q["n_ties"]
+                for i in range(call, 64, 16):
+                    s = gdist.gdist_query(gctx, ha, hbs[i], pa, poses[i], mode)
+                    assert res[i]["distance"] == s["distance"] and res[i]["tri_a"] == s["tri_a"]
+                    ref = oracle_query(orc, A, pa, statics[i], poses[i], mode)
+                    check_against_oracle(orc, res[i], ref, A, pa, statics[i], poses[i], mode)
+        # a released static mesh takes its kept trees along; the others stay
+        gdist.gdist_release(gctx, hbs[5])
+        keep = [h for j, h in enumerate(hbs) if j != 5]
+        kp = [p for j, p in enumerate(poses) if j != 5]
+        gdist.gdist_query_one_to_many(gctx, ha, pa, keep, kp, 0)
+        assert gdist.gdist_last_stats(gctx)["refit_trees"] == 1
+        hbs[5] = build(gctx, statics[5])
+    finally:
+        gdist.gdist_set_option(gctx, "one_to_many", 1)
+        gdist.gdist_release(gctx, ha)
+        for h in hbs:
+            gdist.gdist_release(gctx, h)

@@ -52,3 +52,23 @@ def test_stats_table_and_bench_line(tmp_path):
     md = profsum.stats(str(stats), str(log), "cmd", "title")
     assert "| void gd::k_traverse<true> | 3 | 81.000 | 27000.0 | 10000.0 | 45000.0 | 94.00 |" in md
     assert '"value": 500.0' in md and '"other"' not in md
+
+
+def test_counters_summary(tmp_path):
+    """Per-dispatch means of several counters for the traversal only, and the
+    derived hit rates from their definitions."""
+    p = tmp_path / "c.csv"
+    rows = []
+    for d, name in ((1, "k_traverse<true>"), (2, "k_refit_leaves_batch"), (3, "k_traverse<true>")):
+        for cn, v in (("TCC_HIT_sum", 300.0 * d), ("TCC_MISS_sum", 100.0 * d), ("SQ_WAVES", 10.0),
+                      ("SQ_INSTS_VALU", 1000.0 * d)):
+            rows.append((d, name, cn, v))
+    with open(p, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, name, cn, v in rows:
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": name, "Counter_Name": cn, "Counter_Value": v})
+    out = profsum.counters([str(p)], "cmd", "title")
+    assert "| TCC_HIT_sum | 600 | 2 |" in out          # mean of dispatches 1 and 3: (300 + 900) / 2
+    assert "| L2 hit rate | 0.75 |" in out
+    assert "| VALU instructions per wave | 200 |" in out
