@@ -235,6 +235,24 @@ gdist_status_t gdist_query(gdist_ctx_t ctx, gdist_mesh_t a, gdist_mesh_t b,
                            const gdist_pose_t* pa, const gdist_pose_t* pb,
                            gdist_mode_t mode, gdist_result_t* out);
 
+/* gdist_query for callers that cannot allocate device memory (a serving loop
+ * with a fixed footprint, code that must not call hipMalloc): the same
+ * kernels and the same result as gdist_query, but every device buffer of the
+ * query comes from one fixed array of 128 MiB that the library holds on each
+ * GPU it runs on (set up by gdist_create, kept until the process ends); the
+ * call allocates no device or pinned memory.  Limits: the smaller mesh of the
+ * pair (the one refitted) has fewer than 2^20 triangles (E_INVALID
+ * otherwise, before anything runs); the traversal runs on at most 64
+ * workgroups with a fixed spill stack of 2^20 pairs, and a query that needs
+ * more storage returns E_CAPACITY (out->status too) where gdist_query would
+ * grow its storage.  All calls on one GPU share its array, which keeps the
+ * last call's contents: calls that overlap on one GPU (several threads or
+ * contexts of that device) race and must be serialised by the caller.
+ * E_BUSY while a server runs on the context.  Synchronous. */
+gdist_status_t gdist_query_noalloc(gdist_ctx_t ctx, gdist_mesh_t a, gdist_mesh_t b,
+                                   const gdist_pose_t* pa, const gdist_pose_t* pb,
+                                   gdist_mode_t mode, gdist_result_t* out);
+
 /* n queries in one persistent launch (one refit launch set, one traversal
  * launch, one re-evaluation).  Each query's result equals what gdist_query
  * returns for it alone.  out[i].status carries the per-query status (a query

@@ -18,7 +18,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgdist.so")
 ARCH = os.environ.get("GDIST_ARCH", "gfx950")
 
-SOURCES = ["build.hip", "refit.hip", "traverse.hip", "selfcheck.hip", "api.cpp", "server.cpp"]
+SOURCES = ["build.hip", "refit.hip", "traverse.hip", "selfcheck.hip", "noalloc.hip", "api.cpp", "server.cpp"]
 
 FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -737,6 +737,7 @@ gdist_status_t gdist_create(int device, gdist_ctx_t* out) {
   const char* tr = getenv("GDIST_TRACE");
   c->trace = tr && tr[0] && tr[0] != '0';
   gdist_status_t s = refresh_grid(c);
+  if (s == GDIST_OK) s = noalloc_init(device);
   if (s != GDIST_OK) {
     gdist_destroy(c);
     return s;

@@ -60,6 +60,8 @@ gdist_status_t make_slot(gdist_ctx* c, const gdist_query_desc_t& q, uint32_t idx
 // FP64 re-evaluation) on the context's stream and workspace.
 gdist_status_t run_queries(gdist_ctx* c, uint32_t n, const gdist_query_desc_t* q, gdist_result_t* out);
 void drain_async(gdist_ctx* c);
+// Set up the no-allocation array of `device` (current); once per device.
+gdist_status_t noalloc_init(int device);
 
 }  // namespace gd
 

@@ -130,6 +130,8 @@ def lib():
         "gdist_mesh_export": [vp, u64, fp, fp, fp],
         "gdist_query": [vp, u64, u64, C.POINTER(gdist_pose_t), C.POINTER(gdist_pose_t), C.c_int,
                         C.POINTER(gdist_result_t)],
+        "gdist_query_noalloc": [vp, u64, u64, C.POINTER(gdist_pose_t), C.POINTER(gdist_pose_t), C.c_int,
+                                C.POINTER(gdist_result_t)],
         "gdist_query_batch": [vp, u32, C.POINTER(gdist_query_desc_t), C.POINTER(gdist_result_t)],
         "gdist_query_one_to_many": [vp, u64, C.POINTER(gdist_pose_t), u32, C.POINTER(u64), C.POINTER(gdist_pose_t),
                                     C.c_int, C.POINTER(gdist_result_t)],
@@ -162,7 +164,7 @@ def exported_symbols() -> List[str]:
             "gdist_last_stats", "gdist_last_error", "gdist_eval_box_bounds", "gdist_eval_tri_tri",
             "gdist_server_start", "gdist_server_submit", "gdist_server_poll", "gdist_server_stats",
             "gdist_server_stop", "gdist_query_batch_async", "gdist_sync", "gdist_set_allocator",
-            "gdist_update", "gdist_query_one_to_many"]
+            "gdist_update", "gdist_query_one_to_many", "gdist_query_noalloc"]
 
 
 def gdist_last_error() -> str:
@@ -277,6 +279,15 @@ def gdist_query(ctx: int, a: int, b: int, pose_a, pose_b, mode: int = GDIST_MIN)
     pb = pose_b if isinstance(pose_b, gdist_pose_t) else make_pose(*pose_b)
     r = gdist_result_t()
     _check(lib().gdist_query(ctx, a, b, C.byref(pa), C.byref(pb), int(mode), C.byref(r)))
+    return r.as_dict()
+
+
+def gdist_query_noalloc(ctx: int, a: int, b: int, pose_a, pose_b, mode: int = GDIST_MIN) -> dict:
+    """gdist_query through the entry point that allocates no device memory."""
+    pa = pose_a if isinstance(pose_a, gdist_pose_t) else make_pose(*pose_a)
+    pb = pose_b if isinstance(pose_b, gdist_pose_t) else make_pose(*pose_b)
+    r = gdist_result_t()
+    _check(lib().gdist_query_noalloc(ctx, a, b, C.byref(pa), C.byref(pb), int(mode), C.byref(r)))
     return r.as_dict()
 
 
