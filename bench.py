@@ -186,6 +186,44 @@ def cpu_baseline(workers: int, nu: int, nv: int) -> dict:
             "results": {r[0]: {"distance": r[2], "pair": [r[3], r[4]], "n_ties": r[5]} for r in rows}}
 
 
+def build_timing(mesh, reps: int = 3) -> dict:
+    """gdist_build of the Rings mesh from device-resident arrays (torch
+    tensors), the library's allocations served by torch's caching allocator,
+    median wall time of `reps` builds after one warm-up build."""
+    import torch
+    from paper_2411_11244_amd import gdist
+    ctx = gdist.gdist_create(0)
+    live = {}
+
+    def alloc(n, user):
+        p = torch.cuda.caching_allocator_alloc(int(n))
+        live[p] = int(n)
+        return p
+
+    def free(p, user):
+        live.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+
+    keep = gdist.gdist_set_allocator(ctx, alloc, free)
+    ts = []
+    try:
+        v = torch.from_numpy(mesh.verts).cuda()
+        f = torch.from_numpy(mesh.tris.astype(np.int32)).cuda()
+        for i in range(reps + 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            h = gdist.gdist_build(ctx, v, f)
+            ts.append((time.perf_counter() - t) * 1e3)
+            gdist.gdist_release(ctx, h)
+        del v, f
+    finally:
+        gdist.gdist_destroy(ctx)
+    del keep
+    return {"ms": round(float(np.median(ts[1:])), 3), "tris": int(mesh.n_tris),
+            "input": "device-resident arrays; synchronous call (vertex pass, key pass, 8-pass radix sort, emit, "
+                     "refit of the local tree, two small copies back)"}
+
+
 # ---------------------------------------------------------------- legs
 def leg_tiny(copy_gbs) -> dict:
     import meshgen as g
@@ -432,6 +470,7 @@ def main():
     agree = all(a["distance"] == b["distance"] and (a["tri_a"], a["tri_b"]) == (b["tri_a"], b["tri_b"])
                 for a, b in zip(res, plain_res))
     gdist.gdist_destroy(ctx)
+    build = build_timing(mesh)
 
     # ---- stored oracle results of the Rings frames (tests/golden, written by the oracle)
     verify = None
@@ -484,6 +523,7 @@ def main():
         "roofline": roof,
         "copy_kernel": copy,
         "refit": refit,
+        "build": build,
         "stats_last_step": stats[-1],
         "batched_equals_plain": agree,
         "cpu_baseline": cpu,

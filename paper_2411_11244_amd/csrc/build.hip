@@ -226,8 +226,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t* __restric
 // block's tile (a row = 64 consecutive keys) in order: lanes holding the same
 // digit are found with eight ballots, their order inside the row comes from
 // mbcnt, and a per-wave running count per digit carries the order across
-// rows.  A final per-digit prefix over the four waves makes the block-local
-// rank, added to the digit's global offset for this block.
+// rows.  A per-digit prefix over the four waves and an exclusive scan over the
+// 256 digits give each key its place in the tile sorted by digit; the tile is
+// reordered in LDS, and thread t then writes tile positions t, t + 256, ...
+// to the digit's global offset for this block plus the position inside the
+// digit's run, so consecutive threads store consecutive addresses of one run.
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                             const uint32_t* __restrict__ vin,
                                                             uint64_t* __restrict__ kout,
@@ -235,6 +238,10 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
                                                             uint32_t shift, const uint32_t* __restrict__ offs,
                                                             uint32_t nblocks) {
   __shared__ uint32_t wc[kRsThreads / kWave][257];
+  __shared__ uint32_t lstart[256];
+  __shared__ uint32_t scan_s[kScanThreads];
+  __shared__ uint64_t tk[kRsTile];
+  __shared__ uint32_t tv[kRsTile];
   const uint32_t w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   for (uint32_t i = threadIdx.x; i < (kRsThreads / kWave) * 257; i += kRsThreads) (&wc[0][0])[i] = 0;
   __syncthreads();
@@ -263,7 +270,9 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
   }
   __syncthreads();
   {
-    uint32_t d = threadIdx.x;  // 256 threads, one per digit
+    // per digit: the four waves' offsets inside the digit's run, and the
+    // run's start in the digit-sorted tile
+    const uint32_t d = threadIdx.x;  // 256 threads, one per digit
     uint32_t run = 0;
 #pragma unroll
     for (int q = 0; q < kRsThreads / kWave; ++q) {
@@ -271,33 +280,61 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
       wc[q][d] = run;
       run += c;
     }
+    uint32_t excl;
+    block_exclusive(run, scan_s, &excl);
+    lstart[d] = excl;
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kRsRowsPerWave; ++r) {
     if (dig[r] < 256u) {
-      uint32_t pos = offs[(uint64_t)dig[r] * nblocks + blockIdx.x] + wc[w][dig[r]] + rk[r];
-      kout[pos] = key[r];
-      vout[pos] = val[r];
+      const uint32_t lp = lstart[dig[r]] + wc[w][dig[r]] + rk[r];
+      tk[lp] = key[r];
+      tv[lp] = val[r];
     }
+  }
+  __syncthreads();
+  const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
+  const uint32_t valid = n - tile0 < (uint64_t)kRsTile ? (uint32_t)(n - tile0) : (uint32_t)kRsTile;
+  for (uint32_t i = threadIdx.x; i < valid; i += kRsThreads) {
+    const uint64_t k = tk[i];
+    const uint32_t d = (uint32_t)((k >> shift) & 255u);
+    const uint32_t pos = offs[(uint64_t)d * nblocks + blockIdx.x] + (i - lstart[d]);
+    kout[pos] = k;
+    vout[pos] = tv[i];
   }
 }
 
 // Triangles in sorted (= leaf) order, plus the caller index of each.
-__global__ void k_emit(const float* __restrict__ v, const uint32_t* __restrict__ f, uint32_t nt,
-                       const uint32_t* __restrict__ sorted, float* __restrict__ tris, uint32_t* __restrict__ orig,
-                       uint32_t* __restrict__ fl) {
-  uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nt) return;
-  uint32_t o = sorted[s];
-  orig[s] = o;
+// The 256 triangles of a workgroup are gathered into LDS, then written out
+// as one contiguous block (9,216 bytes at a 16-byte aligned offset) with
+// 16-byte stores.
+constexpr int kEmitThreads = 256;
+__global__ __launch_bounds__(kEmitThreads) void k_emit(const float* __restrict__ v, const uint32_t* __restrict__ f,
+                                                       uint32_t nt, const uint32_t* __restrict__ sorted,
+                                                       float* __restrict__ tris, uint32_t* __restrict__ orig,
+                                                       uint32_t* __restrict__ fl) {
+  __shared__ __align__(16) float st[9 * kEmitThreads];
+  const uint64_t s0 = (uint64_t)blockIdx.x * kEmitThreads;
+  const uint64_t s = s0 + threadIdx.x;
+  if (s < nt) {
+    const uint32_t o = sorted[s];
+    orig[s] = o;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    uint32_t vi = f[3ull * o + c];
-    if (fl) fl[3ull * s + c] = vi;
+    for (int c = 0; c < 3; ++c) {
+      const uint32_t vi = f[3ull * o + c];
+      if (fl) fl[3ull * s + c] = vi;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) tris[9 * s + 3 * c + k] = v[3ull * vi + k];
+      for (int k = 0; k < 3; ++k) st[9 * threadIdx.x + 3 * c + k] = v[3ull * vi + k];
+    }
   }
+  __syncthreads();
+  const uint32_t cnt = nt - s0 < (uint64_t)kEmitThreads ? (uint32_t)(nt - s0) : (uint32_t)kEmitThreads;
+  const uint32_t nf = 9u * cnt, n4 = nf >> 2;
+  float* out = tris + 9ull * s0;     // 36 * 256 * blockIdx.x bytes: 16-byte aligned
+  for (uint32_t i = threadIdx.x; i < n4; i += kEmitThreads)
+    *reinterpret_cast<f4v*>(out + 4u * i) = *reinterpret_cast<const f4v*>(st + 4u * i);
+  for (uint32_t i = 4u * n4 + threadIdx.x; i < nf; i += kEmitThreads) out[i] = st[i];
 }
 
 // Deformable meshes: the triangles, in the leaf order of the original build,
@@ -360,7 +397,7 @@ hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp,
 
 hipError_t launch_emit(const float* v, const uint32_t* f, uint32_t nt, const uint32_t* sorted, float* tris,
                        uint32_t* orig, uint32_t* fl, hipStream_t s) {
-  k_emit<<<(nt + 255) / 256, 256, 0, s>>>(v, f, nt, sorted, tris, orig, fl);
+  k_emit<<<(nt + kEmitThreads - 1) / kEmitThreads, kEmitThreads, 0, s>>>(v, f, nt, sorted, tris, orig, fl);
   return hipGetLastError();
 }
 

@@ -113,6 +113,16 @@ __device__ __forceinline__ void load_tri_xf(const float* __restrict__ tris, uint
   for (int k = 0; k < 3; ++k) xform(T, v[3 * k], v[3 * k + 1], v[3 * k + 2], o + 3 * k);
 }
 
+// Square root and reciprocal square root of the FP32 path: the hardware
+// instructions, within 1 ulp for normal inputs (the IEEE-rounded library
+// forms cost about fifteen and five instructions each).  A squared distance
+// below the smallest normal float (distances below 2^-63) may lose its
+// relative accuracy, an absolute error below 2^-63, which the error window
+// covers because the traversal floors its coordinate scale M at 2^-40.  Every
+// FP32 value of the path is widened by that window; final values are FP64.
+__device__ __forceinline__ float sqrt32(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rsqrt32(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // --------------------------------------------------------------------------
 // AABB bounds (Sec. 4)
 // --------------------------------------------------------------------------
@@ -132,7 +142,7 @@ __device__ __forceinline__ float min_lower(const Box& a, const Box& b) {
     float gap = fmaxf(0.f, fmaxf(b.lo[i] - a.hi[i], a.lo[i] - b.hi[i]));
     sgap += gap * gap;
   }
-  return sqrtf(sgap);
+  return sqrt32(sgap);
 }
 
 // Enhanced d_min^U (Sec. 4): the smallest, over the 36 pairs of a face of A
@@ -142,7 +152,7 @@ __device__ __forceinline__ float min_upper(const Box& a, const Box& b, bool enha
   float F[3], G[3], H[3], E[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) F[i] = sq(fmaxf(b.hi[i] - a.lo[i], a.hi[i] - b.lo[i]));   // full intervals
-  if (!enhanced) return sqrtf(F[0] + F[1] + F[2]);
+  if (!enhanced) return sqrt32(F[0] + F[1] + F[2]);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     // A's face flat on axis i at a in {lo, hi} against B's full interval
@@ -164,7 +174,7 @@ __device__ __forceinline__ float min_upper(const Box& a, const Box& b, bool enha
   m = fminf(m, E[0] + (F[1] + F[2]));
   m = fminf(m, E[1] + (F[0] + F[2]));
   m = fminf(m, E[2] + (F[0] + F[1]));
-  return sqrtf(m);
+  return sqrt32(m);
 }
 
 // Min-distance bounds of two boxes: `lower` = conventional d_min^L,
@@ -181,7 +191,7 @@ __device__ __forceinline__ float max_upper(const Box& a, const Box& b) {
   float F = 0.f;
 #pragma unroll
   for (int i = 0; i < 3; ++i) F += sq(fmaxf(b.hi[i] - a.lo[i], a.hi[i] - b.lo[i]));
-  return sqrtf(F);
+  return sqrt32(F);
 }
 
 // Enhanced d_max^L (Sec. 4, the mirror image for the maximum): the largest,
@@ -194,7 +204,7 @@ __device__ __forceinline__ float max_lower(const Box& a, const Box& b, bool enha
     float gap = fmaxf(0.f, fmaxf(b.lo[i] - a.hi[i], a.lo[i] - b.hi[i]));
     Gp[i] = gap * gap;
   }
-  if (!enhanced) return sqrtf(Gp[0] + Gp[1] + Gp[2]);
+  if (!enhanced) return sqrt32(Gp[0] + Gp[1] + Gp[2]);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     // point a (a face of A flat on axis i) against B's interval: its gap
@@ -214,7 +224,7 @@ __device__ __forceinline__ float max_lower(const Box& a, const Box& b, bool enha
   m = fmaxf(m, E[0] + (Gp[1] + Gp[2]));
   m = fmaxf(m, E[1] + (Gp[0] + Gp[2]));
   m = fmaxf(m, E[2] + (Gp[0] + Gp[1]));
-  return sqrtf(m);
+  return sqrt32(m);
 }
 
 // Max-distance bounds: `upper` = conventional d_max^U, `lower` = enhanced

@@ -33,10 +33,10 @@ __global__ void k_eval_tri_tri(uint32_t n, const float* __restrict__ p, const fl
     Qd[v] = mk<double>(Q[v].x, Q[v].y, Q[v].z);
   }
   if (mode == 0) {
-    o32[i] = sqrtf(tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr));
+    o32[i] = sqrt32(tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr));
     o64[i] = sqrt(tri_tri_min_d2<double, false>(Pd, Qd, nullptr, nullptr));
   } else {
-    o32[i] = sqrtf(tri_tri_max_d2<float, false>(P, Q, nullptr, nullptr));
+    o32[i] = sqrt32(tri_tri_max_d2<float, false>(P, Q, nullptr, nullptr));
     o64[i] = sqrt(tri_tri_max_d2<double, false>(Pd, Qd, nullptr, nullptr));
   }
 }

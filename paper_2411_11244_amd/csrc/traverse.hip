@@ -220,13 +220,13 @@ __device__ __forceinline__ float sep_lower(const V3<float>* P, const V3<float>* 
   float lb = 0.f;
   const V3<float> n = cross(P[1] - P[0], P[2] - P[0]);
   const float nn = dot(n, n);
-  if (nn >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], n) * rsqrtf(nn));
+  if (nn >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], n) * rsqrt32(nn));
   const V3<float> m = cross(Q[1] - Q[0], Q[2] - Q[0]);
   const float mm = dot(m, m);
-  if (mm >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], m) * rsqrtf(mm));
+  if (mm >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], m) * rsqrt32(mm));
   const V3<float> u = (Q[0] + Q[1] + Q[2]) - (P[0] + P[1] + P[2]);
   const float uu = dot(u, u);
-  if (uu >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], u) * rsqrtf(uu));
+  if (uu >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], u) * rsqrt32(uu));
   return lb;
 }
 
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
 #pragma unroll
   for (int k = 0; k < 3; ++k)
     M = fmaxf(M, fmaxf(fmaxf(fabsf(ra.lo[k]), fabsf(ra.hi[k])), fmaxf(fabsf(rb.lo[k]), fabsf(rb.hi[k]))));
-  M = fmaxf(fmaxf(M, d.m_floor), 1e-30f);
+  M = fmaxf(fmaxf(M, d.m_floor), 0x1p-40f);   // the FP32 square roots need M >= 2^-40
   const float delta = d.kappa_u * M;
   float key, best;
   if (mode == 0) {
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
     if (act) {
       V3<float> P[3], Q[3];
       load_pair(&d, pa, pb, P, Q);
-      dd = sqrtf(mode == 0 ? tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr)
+      dd = sqrt32(mode == 0 ? tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr)
                            : tri_tri_max_d2<float, false>(P, Q, nullptr, nullptr));
     }
     if (mode == 0) best = fminf(best, wave_min(dd) + delta);
@@ -333,7 +333,7 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
     if (lane == 0) {
       V3<float> P[3], Q[3];
       load_pair(&d, d.hint_a, d.hint_b, P, Q);
-      dd = sqrtf(mode == 0 ? tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr)
+      dd = sqrt32(mode == 0 ? tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr)
                            : tri_tri_max_d2<float, false>(P, Q, nullptr, nullptr));
     }
     if (mode == 0) best = fminf(best, wave_min(dd) + delta);
@@ -898,7 +898,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
       bool cand = false;
       float dd = 0.f;
       if (full) {
-        dd = sqrtf(tri_tri_max_d2<float, false>(P[s4 & 1], Q[s4 >> 1], nullptr, nullptr));
+        dd = sqrt32(tri_tri_max_d2<float, false>(P[s4 & 1], Q[s4 >> 1], nullptr, nullptr));
         imp = fmaxf(imp, fmaxf(dd - delta, 0.f));
         cand = dd + delta >= best;
       }
@@ -936,7 +936,7 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
         Q[w] = mk<float>(b[3 * w], b[3 * w + 1], b[3 * w + 2]);
       }
     }
-    dd = sqrtf(mode == 0 ? tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr)
+    dd = sqrt32(mode == 0 ? tri_tri_min_d2<float, false>(P, Q, nullptr, nullptr)
                          : tri_tri_max_d2<float, false>(P, Q, nullptr, nullptr));
     const float best = v.best;
     if (mode == 0) {
