@@ -207,27 +207,51 @@ __device__ __forceinline__ void load_pair(const SlotDesc* d, uint32_t pa, uint32
 // normal's direction (large for slivers) cannot make the bound exceed the
 // distance; only the rounding of the projections themselves remains, which is
 // a few units of 2^-24 times the coordinates' magnitude, inside the error
-// window.  An axis whose squared length is not a normal float is skipped.
-// Zero when no axis separates.
-__device__ __forceinline__ float axis_gap(const V3<float>* P, const V3<float>* Q, V3<float> o, V3<float> n) {
-  const float p0 = dot(n, P[0] - o), p1 = dot(n, P[1] - o), p2 = dot(n, P[2] - o);
-  const float q0 = dot(n, Q[0] - o), q1 = dot(n, Q[1] - o), q2 = dot(n, Q[2] - o);
-  const float pmin = fminf(p0, fminf(p1, p2)), pmax = fmaxf(p0, fmaxf(p1, p2));
-  const float qmin = fminf(q0, fminf(q1, q2)), qmax = fmaxf(q0, fmaxf(q1, q2));
-  return fmaxf(qmin - pmax, pmin - qmax);
+// window.  An axis whose squared length is below 1e-30 is skipped.  Zero when
+// no axis separates.
+//
+// What depends on one triangle only (its normal, the normal's inverse
+// length, the triangle's own interval on its normal measured from its first
+// vertex, its vertex sum) is computed once per triangle and shared by the
+// pairs it takes part in.
+struct TriAxes {
+  V3<float> n, sum;
+  float inv, lo, hi;
+};
+__device__ __forceinline__ TriAxes tri_axes(const V3<float>* T) {
+  TriAxes t;
+  const V3<float> e1 = T[1] - T[0], e2 = T[2] - T[0];
+  t.n = cross(e1, e2);
+  const float nn = dot(t.n, t.n);
+  t.inv = nn >= 1e-30f ? rsqrt32(nn) : 0.f;
+  const float p1 = dot(t.n, e1), p2 = dot(t.n, e2);
+  t.lo = fminf(0.f, fminf(p1, p2));
+  t.hi = fmaxf(0.f, fmaxf(p1, p2));
+  t.sum = (T[0] + T[1]) + T[2];
+  return t;
 }
-__device__ __forceinline__ float sep_lower(const V3<float>* P, const V3<float>* Q) {
-  float lb = 0.f;
-  const V3<float> n = cross(P[1] - P[0], P[2] - P[0]);
-  const float nn = dot(n, n);
-  if (nn >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], n) * rsqrt32(nn));
-  const V3<float> m = cross(Q[1] - Q[0], Q[2] - Q[0]);
-  const float mm = dot(m, m);
-  if (mm >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], m) * rsqrt32(mm));
-  const V3<float> u = (Q[0] + Q[1] + Q[2]) - (P[0] + P[1] + P[2]);
+__device__ __forceinline__ float sep_lower(const V3<float>* P, const TriAxes& a, const V3<float>* Q,
+                                           const TriAxes& b) {
+  // Q's vertices and P's edges, both from P's first vertex
+  const V3<float> d0 = Q[0] - P[0], d1 = Q[1] - P[0], d2 = Q[2] - P[0];
+  const V3<float> e1 = P[1] - P[0], e2 = P[2] - P[0];
+  // P's normal: Q against P's own interval
+  const float q0 = dot(a.n, d0), q1 = dot(a.n, d1), q2 = dot(a.n, d2);
+  float lb = fmaxf(fminf(q0, fminf(q1, q2)) - a.hi, a.lo - fmaxf(q0, fmaxf(q1, q2))) * a.inv;
+  // Q's normal: P from Q's first vertex (P0 - Q0 = -d0, Pk - Q0 = ek - d0) against Q's own interval
+  const float c = dot(b.n, d0);
+  const float r0 = -c, r1 = dot(b.n, e1) - c, r2 = dot(b.n, e2) - c;
+  lb = fmaxf(lb, fmaxf(fminf(r0, fminf(r1, r2)) - b.hi, b.lo - fmaxf(r0, fmaxf(r1, r2))) * b.inv);
+  // centroid axis, both sets from P's first vertex
+  const V3<float> u = b.sum - a.sum;
   const float uu = dot(u, u);
-  if (uu >= 1e-30f) lb = fmaxf(lb, axis_gap(P, Q, P[0], u) * rsqrt32(uu));
-  return lb;
+  const float iu = uu >= 1e-30f ? rsqrt32(uu) : 0.f;
+  const float s1 = dot(u, e1), s2 = dot(u, e2);
+  const float t0 = dot(u, d0), t1 = dot(u, d1), t2 = dot(u, d2);
+  const float pmin = fminf(0.f, fminf(s1, s2)), pmax = fmaxf(0.f, fmaxf(s1, s2));
+  const float qmin = fminf(t0, fminf(t1, t2)), qmax = fmaxf(t0, fmaxf(t1, t2));
+  lb = fmaxf(lb, fmaxf(qmin - pmax, pmin - qmax) * iu);
+  return fmaxf(lb, 0.f);
 }
 
 // Zero the control block and the segment counts of the first round's buffers;
@@ -885,13 +909,22 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
     }
   }
   const bool any_max = __ballot(act && mode != 0) != 0ull;   // wave-uniform
+  const bool any_min = __ballot(act && mode == 0) != 0ull;
   float imp = 0.f;   // max mode: the lane's best improvement of the bound
+  // pairs in the order (P0,Q0), (P1,Q0), (P0,Q1), (P1,Q1): A's two triangles'
+  // axes stay in registers, B's are computed when B's triangle changes
+  TriAxes AP[2], aq;
+  if (any_min) {
+    AP[0] = tri_axes(P[0]);
+    AP[1] = tri_axes(P[1]);
+  }
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4) {
     const uint32_t pa = sa + (s4 & 1), pb = sb + (s4 >> 1);
     const bool valid = act && pa < ea && pb < eb;
+    if (any_min && (s4 & 1) == 0) aq = tri_axes(Q[s4 >> 1]);
     bool pass = valid && mode == 0;
-    if (pass) pass = sep_lower(P[s4 & 1], Q[s4 >> 1]) - delta <= best;
+    if (pass) pass = sep_lower(P[s4 & 1], AP[s4 & 1], Q[s4 >> 1], aq) - delta <= best;
     add_stat(ws, ST_TRI, valid);
     if (any_max) {
       const bool full = valid && mode != 0;
