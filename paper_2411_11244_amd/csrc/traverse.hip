@@ -200,22 +200,40 @@ __device__ __forceinline__ void load_pair(const SlotDesc* d, uint32_t pa, uint32
 }
 
 // Lower bound of the distance between triangles P and Q from three candidate
-// separating axes: the normal of P, the normal of Q, and the line through the
-// two centroids.  Both vertex sets are projected onto each axis and the gap
+// separating axes: the line through the two centroids, the normal of P and
+// the normal of Q.  Both vertex sets are projected onto each axis and the gap
 // between the two intervals is the bound: a projection never increases
-// distances, whatever direction the axis has, so the FP32 rounding of a
-// normal's direction (large for slivers) cannot make the bound exceed the
-// distance; only the rounding of the projections themselves remains, which is
-// a few units of 2^-24 times the coordinates' magnitude, inside the error
-// window.  An axis whose squared length is below 1e-30 is skipped.  Zero when
-// no axis separates.
+// distances, whatever direction the axis has, so the FP32 rounding of an
+// axis's direction (large for the normal of a sliver) cannot make the bound
+// exceed the distance; only the rounding of the projections themselves
+// remains, which is a few units of 2^-24 times the coordinates' magnitude,
+// inside the error window.  An axis whose squared length is below 1e-30 is
+// skipped.  Zero when no axis separates.
 //
-// What depends on one triangle only (its normal, the normal's inverse
-// length, the triangle's own interval on its normal measured from its first
-// vertex, its vertex sum) is computed once per triangle and shared by the
-// pairs it takes part in.
+// The centroid axis alone rejects almost every pair the normals reject (on
+// two interlocked tori of 7.5M triangles each, over 100 poses, 8.35e9
+// triangle pairs leave 1.15e6 after it and 1.12e6 after all three), so the
+// filter tests it first for all of a lane's pairs and computes the normals
+// only when some lane of the wave still has a surviving pair.
+
+// Centroid axis: sp and sq are the triangles' vertex sums (three times the centroids).
+__device__ __forceinline__ float sep_centroid(const V3<float>* P, V3<float> sp, const V3<float>* Q, V3<float> sq) {
+  const V3<float> u = sq - sp;
+  const float uu = dot(u, u);
+  const float iu = uu >= 1e-30f ? rsqrt32(uu) : 0.f;
+  // both sets from P's first vertex
+  const float s1 = dot(u, P[1] - P[0]), s2 = dot(u, P[2] - P[0]);
+  const float t0 = dot(u, Q[0] - P[0]), t1 = dot(u, Q[1] - P[0]), t2 = dot(u, Q[2] - P[0]);
+  const float pmin = fminf(0.f, fminf(s1, s2)), pmax = fmaxf(0.f, fmaxf(s1, s2));
+  const float qmin = fminf(t0, fminf(t1, t2)), qmax = fmaxf(t0, fmaxf(t1, t2));
+  return fmaxf(fmaxf(qmin - pmax, pmin - qmax) * iu, 0.f);
+}
+
+// What depends on one triangle only for the normal axes: its normal, the
+// normal's inverse length (0 when degenerate) and the triangle's own interval
+// on its normal, measured from its first vertex.
 struct TriAxes {
-  V3<float> n, sum;
+  V3<float> n;
   float inv, lo, hi;
 };
 __device__ __forceinline__ TriAxes tri_axes(const V3<float>* T) {
@@ -227,11 +245,11 @@ __device__ __forceinline__ TriAxes tri_axes(const V3<float>* T) {
   const float p1 = dot(t.n, e1), p2 = dot(t.n, e2);
   t.lo = fminf(0.f, fminf(p1, p2));
   t.hi = fmaxf(0.f, fmaxf(p1, p2));
-  t.sum = (T[0] + T[1]) + T[2];
   return t;
 }
-__device__ __forceinline__ float sep_lower(const V3<float>* P, const TriAxes& a, const V3<float>* Q,
-                                           const TriAxes& b) {
+// Normal axes of P and Q.
+__device__ __forceinline__ float sep_normals(const V3<float>* P, const TriAxes& a, const V3<float>* Q,
+                                             const TriAxes& b) {
   // Q's vertices and P's edges, both from P's first vertex
   const V3<float> d0 = Q[0] - P[0], d1 = Q[1] - P[0], d2 = Q[2] - P[0];
   const V3<float> e1 = P[1] - P[0], e2 = P[2] - P[0];
@@ -242,15 +260,6 @@ __device__ __forceinline__ float sep_lower(const V3<float>* P, const TriAxes& a,
   const float c = dot(b.n, d0);
   const float r0 = -c, r1 = dot(b.n, e1) - c, r2 = dot(b.n, e2) - c;
   lb = fmaxf(lb, fmaxf(fminf(r0, fminf(r1, r2)) - b.hi, b.lo - fmaxf(r0, fmaxf(r1, r2))) * b.inv);
-  // centroid axis, both sets from P's first vertex
-  const V3<float> u = b.sum - a.sum;
-  const float uu = dot(u, u);
-  const float iu = uu >= 1e-30f ? rsqrt32(uu) : 0.f;
-  const float s1 = dot(u, e1), s2 = dot(u, e2);
-  const float t0 = dot(u, d0), t1 = dot(u, d1), t2 = dot(u, d2);
-  const float pmin = fminf(0.f, fminf(s1, s2)), pmax = fmaxf(0.f, fmaxf(s1, s2));
-  const float qmin = fminf(t0, fminf(t1, t2)), qmax = fmaxf(t0, fmaxf(t1, t2));
-  lb = fmaxf(lb, fmaxf(qmin - pmax, pmin - qmax) * iu);
   return fmaxf(lb, 0.f);
 }
 
@@ -911,20 +920,39 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
   const bool any_max = __ballot(act && mode != 0) != 0ull;   // wave-uniform
   const bool any_min = __ballot(act && mode == 0) != 0ull;
   float imp = 0.f;   // max mode: the lane's best improvement of the bound
-  // pairs in the order (P0,Q0), (P1,Q0), (P0,Q1), (P1,Q1): A's two triangles'
-  // axes stay in registers, B's are computed when B's triangle changes
-  TriAxes AP[2], aq;
+  // centroid axis for every pair of the lane (pairs in the order (P0,Q0),
+  // (P1,Q0), (P0,Q1), (P1,Q1)); the normal axes only if a pair survives it
+  bool pass4[4];
   if (any_min) {
-    AP[0] = tri_axes(P[0]);
-    AP[1] = tri_axes(P[1]);
+    V3<float> SP[2], SQ[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      SP[i] = (P[i][0] + P[i][1]) + P[i][2];
+      SQ[i] = (Q[i][0] + Q[i][1]) + Q[i][2];
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const bool valid = act && mode == 0 && sa + (s4 & 1) < ea && sb + (s4 >> 1) < eb;
+      pass4[s4] = valid && sep_centroid(P[s4 & 1], SP[s4 & 1], Q[s4 >> 1], SQ[s4 >> 1]) - delta <= best;
+    }
+    if (__ballot(pass4[0] || pass4[1] || pass4[2] || pass4[3])) {
+      const TriAxes AP0 = tri_axes(P[0]), AP1 = tri_axes(P[1]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const TriAxes aq = tri_axes(Q[j]);
+        if (pass4[2 * j]) pass4[2 * j] = sep_normals(P[0], AP0, Q[j], aq) - delta <= best;
+        if (pass4[2 * j + 1]) pass4[2 * j + 1] = sep_normals(P[1], AP1, Q[j], aq) - delta <= best;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) pass4[s4] = false;
   }
 #pragma unroll
   for (int s4 = 0; s4 < 4; ++s4) {
     const uint32_t pa = sa + (s4 & 1), pb = sb + (s4 >> 1);
     const bool valid = act && pa < ea && pb < eb;
-    if (any_min && (s4 & 1) == 0) aq = tri_axes(Q[s4 >> 1]);
-    bool pass = valid && mode == 0;
-    if (pass) pass = sep_lower(P[s4 & 1], AP[s4 & 1], Q[s4 >> 1], aq) - delta <= best;
+    const bool pass = pass4[s4];
     add_stat(ws, ST_TRI, valid);
     if (any_max) {
       const bool full = valid && mode != 0;
