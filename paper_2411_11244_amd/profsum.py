@@ -30,6 +30,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/traverse.hip", "csrc/gdist_dev.hpp", "csrc/internal.hpp", "tuning/rings_mi355x.json")
 CALIB_MARK = "elementwise"          # the calibration copy is torch's elementwise kernel
 TRAVERSE = "k_traverse"
+XCDS, CUS, SIMDS = 8, 256, 1024    # MI355X
 
 
 def sources_sha256() -> str:
@@ -106,6 +107,20 @@ def counters(csvs, cmds: str, title: str) -> str:
         der.append(("VALU instructions per wave", v["SQ_INSTS_VALU"] / max(1.0, v["SQ_WAVES"])))
     if "TCC_HIT_sum" in v and "TCC_MISS_sum" in v:
         der.append(("L2 hit rate", v["TCC_HIT_sum"] / max(1.0, v["TCC_HIT_sum"] + v["TCC_MISS_sum"])))
+    # MI355X: 8 XCDs (GRBM_GUI_ACTIVE is their sum), 256 CUs, 1,024 SIMDs; the
+    # SQ cycle counters count 4-cycle units
+    if "SQ_ACTIVE_INST_VALU" in v and "GRBM_GUI_ACTIVE" in v:
+        cyc = v["GRBM_GUI_ACTIVE"] / XCDS
+        der.append(("VALU busy (SQ_ACTIVE_INST_VALU x 4 / 1024 SIMDs / GPU cycles)",
+                    v["SQ_ACTIVE_INST_VALU"] * 4.0 / SIMDS / max(1.0, cyc)))
+        if "TA_TA_BUSY_sum" in v:
+            der.append(("texture address unit busy (TA_TA_BUSY / 256 CUs / GPU cycles)",
+                        v["TA_TA_BUSY_sum"] / CUS / max(1.0, cyc)))
+        if "TCP_PENDING_STALL_CYCLES_sum" in v:
+            der.append(("L1 stalled on pending misses (per CU / GPU cycles)",
+                        v["TCP_PENDING_STALL_CYCLES_sum"] / CUS / max(1.0, cyc)))
+    if "SQ_THREAD_CYCLES_VALU" in v and "SQ_ACTIVE_INST_VALU" in v:
+        der.append(("lanes active per VALU instruction", v["SQ_THREAD_CYCLES_VALU"] / max(1.0, 64.0 * v["SQ_ACTIVE_INST_VALU"])))
     if "TCP_TCC_READ_REQ_sum" in v and "TCP_TOTAL_CACHE_ACCESSES_sum" in v:
         der.append(("L1 hit rate (1 - L1-to-L2 reads / L1 accesses)",
                     1.0 - v["TCP_TCC_READ_REQ_sum"] / max(1.0, v["TCP_TOTAL_CACHE_ACCESSES_sum"])))
