@@ -832,9 +832,9 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
   const bool deformable = (flags & GDIST_BUILD_DEFORMABLE) != 0;
   gdist_status_t s = GDIST_OK;
   // temporaries
-  void *dv = nullptr, *df = nullptr, *keys = nullptr, *keys2 = nullptr, *vals = nullptr, *vals2 = nullptr,
-       *hist = nullptr, *misc = nullptr;
-  const size_t vb = 12ull * nv, fb = 12ull * nt, hb = 4ull * radix_hist_words(nt);
+  void *dv = nullptr, *df = nullptr, *keys = nullptr, *keys2 = nullptr, *sortws = nullptr, *misc = nullptr;
+  const size_t vb = 12ull * nv, fb = 12ull * nt, wb = sort_workspace_bytes(nt);
+  const size_t mb = 64 + vertex_pass_scratch_bytes();
   Mesh* m = new Mesh();
   m->n_tris = nt;
   m->n_verts = nv;
@@ -848,10 +848,8 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
     }
     dfree(c, keys, 8ull * nt);
     dfree(c, keys2, 8ull * nt);
-    dfree(c, vals, 4ull * nt);
-    dfree(c, vals2, 4ull * nt);
-    dfree(c, hist, hb);
-    dfree(c, misc, 64);
+    dfree(c, sortws, wb);
+    dfree(c, misc, mb);
   };
   auto abort_build = [&](gdist_status_t st) {
     std::string msg = t_err;
@@ -880,41 +878,39 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
     TRYHIP(hipMemcpyAsync(dv, verts, vb, hipMemcpyHostToDevice, c->stream));
     TRYHIP(hipMemcpyAsync(df, tris, fb, hipMemcpyHostToDevice, c->stream));
   }
-  TRY(dalloc(c, 64, &misc));
+  TRY(dalloc(c, mb, &misc));
   TRY(dalloc(c, 8ull * nt, &keys));
-  TRY(dalloc(c, 4ull * nt, &vals));
-  int* vbox = (int*)misc;
-  uint32_t* vflags = (uint32_t*)((char*)misc + 32);
-  // vertex pass and key pass; the keys are used only once both checks passed
-  TRYHIP(launch_vertex_pass((const float*)dv, nv, vbox, vflags, c->stream));
-  TRYHIP(launch_keys((const float*)dv, nv, (const uint32_t*)df, nt, vbox, (uint64_t*)keys, (uint32_t*)vals, vflags,
-                     c->stream));
-  uint32_t hflags = 0;
-  int hrmax = 0;
-  TRYHIP(hipMemcpyAsync(&hflags, vflags, 4, hipMemcpyDeviceToHost, c->stream));
-  TRYHIP(hipMemcpyAsync(&hrmax, vbox + 6, 4, hipMemcpyDeviceToHost, c->stream));
-  TRYHIP(hipStreamSynchronize(c->stream));
-  std::memcpy(&m->rmax, &hrmax, 4);   // a non-negative float: its ordered int is its bits
-  if (hflags & 1u) return abort_build(fail(GDIST_E_INVALID, "a triangle index is >= n_verts (%u)", nv));
-  if (hflags & 2u) return abort_build(fail(GDIST_E_INVALID, "a vertex coordinate is not finite"));
   TRY(dalloc(c, 8ull * nt, &keys2));
-  TRY(dalloc(c, 4ull * nt, &vals2));
-  TRY(dalloc(c, hb, &hist));
+  TRY(dalloc(c, wb, &sortws));
   TRY(dalloc(c, 36ull * nt, (void**)&m->tris));
   TRY(dalloc(c, 4ull * nt, (void**)&m->orig));
   TRY(dalloc(c, 48ull * m->L, (void**)&m->boxes));
   if (deformable) TRY(dalloc(c, 12ull * nt, (void**)&m->fl));
+  int* vbox = (int*)misc;
+  uint32_t* vflags = (uint32_t*)((char*)misc + 32);
+  // One pass over the device without a host round trip: the vertex and index
+  // checks raise flags that are read at the end (the gathers clamp vertex
+  // indices, so a rejected mesh reads nothing out of bounds).
+  TRYHIP(launch_vertex_pass((const float*)dv, nv, vbox, vflags, (int*)((char*)misc + 64), c->stream));
+  TRYHIP(launch_keys((const float*)dv, nv, (const uint32_t*)df, nt, vbox, (uint64_t*)keys, vflags, c->stream));
   int in_tmp = 0;
-  TRYHIP(launch_radix_sort((uint64_t*)keys, (uint32_t*)vals, (uint64_t*)keys2, (uint32_t*)vals2, nt,
-                           (uint32_t*)hist, c->stream, &in_tmp));
-  const uint32_t* sorted = (const uint32_t*)(in_tmp ? vals2 : vals);
-  TRYHIP(launch_emit((const float*)dv, (const uint32_t*)df, nt, sorted, m->tris, m->orig, m->fl, c->stream));
-  Xf32 I;
-  std::memset(&I, 0, sizeof(I));
-  I.R[0] = I.R[4] = I.R[8] = 1.f;
-  TRYHIP(launch_refit(m->tris, nt, m->L, I, m->boxes, c->stream));
+  const KeyLayout kl = key_layout(nt);
+  TRYHIP(launch_sort((uint64_t*)keys, (uint64_t*)keys2, nt, kl.index_bits, 3u * kl.axis_bits, sortws, c->stream,
+                     &in_tmp));
+  const uint64_t* sorted = (const uint64_t*)(in_tmp ? keys2 : keys);
+  TRYHIP(launch_emit_tree((const float*)dv, nv, (const uint32_t*)df, nt, sorted, kl.index_bits, m->L, m->tris, m->orig,
+                          m->fl, m->boxes, c->stream));
+  int hv[9] = {0};   // vertex box, largest norm, pad, flags
+  uint32_t sort_timeout = 0;
+  TRYHIP(hipMemcpyAsync(hv, misc, 36, hipMemcpyDeviceToHost, c->stream));
   TRYHIP(hipMemcpyAsync(m->root, m->boxes + 6, 24, hipMemcpyDeviceToHost, c->stream));
+  TRYHIP(hipMemcpyAsync(&sort_timeout, sort_timeout_flag(sortws), 4, hipMemcpyDeviceToHost, c->stream));
   TRYHIP(hipStreamSynchronize(c->stream));
+  const uint32_t hflags = (uint32_t)hv[8];
+  std::memcpy(&m->rmax, &hv[6], 4);   // a non-negative float: its ordered int is its bits
+  if (hflags & 1u) return abort_build(fail(GDIST_E_INVALID, "a triangle index is >= n_verts (%u)", nv));
+  if (hflags & 2u) return abort_build(fail(GDIST_E_INVALID, "a vertex coordinate is not finite"));
+  if (sort_timeout) return abort_build(fail(GDIST_E_DEVICE, "the radix sort's look-back wait timed out"));
 #undef TRY
 #undef TRYHIP
   cleanup();
@@ -960,14 +956,16 @@ gdist_status_t gdist_update(gdist_ctx_t c, gdist_mesh_t h, const float* verts, u
   if (!(flags & GDIST_BUILD_DEVICE_PTR)) {
     if ((s = dalloc(c, vb, &dv)) != GDIST_OK) return s;
   }
-  if ((s = dalloc(c, 64, &misc)) == GDIST_OK) {
+  const size_t mb = 64 + vertex_pass_scratch_bytes();
+  if ((s = dalloc(c, mb, &misc)) == GDIST_OK) {
     hipError_t e = hipSuccess;
     if (!(flags & GDIST_BUILD_DEVICE_PTR)) e = hipMemcpyAsync(dv, verts, vb, hipMemcpyHostToDevice, c->stream);
     // finiteness before anything of the mesh changes (the leaf-order indices
     // were checked when the mesh was built)
     uint32_t hflags = 0;
     uint32_t* vflags = (uint32_t*)((char*)misc + 32);
-    if (e == hipSuccess) e = launch_vertex_pass((const float*)dv, nv, (int*)misc, vflags, c->stream);
+    if (e == hipSuccess)
+      e = launch_vertex_pass((const float*)dv, nv, (int*)misc, vflags, (int*)((char*)misc + 64), c->stream);
     int hrmax = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&hflags, vflags, 4, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&hrmax, (int*)misc + 6, 4, hipMemcpyDeviceToHost, c->stream);
@@ -991,7 +989,7 @@ gdist_status_t gdist_update(gdist_ctx_t c, gdist_mesh_t h, const float* verts, u
   }
   (void)hipStreamSynchronize(c->stream);
   if (!(flags & GDIST_BUILD_DEVICE_PTR)) dfree(c, dv, vb);
-  dfree(c, misc, 64);
+  dfree(c, misc, mb);
   if (s == GDIST_OK) drop_world_trees(c, h);   // refitted from the old vertices
   return s;
 }

@@ -5,10 +5,17 @@
 // with the identity transform.
 //
 // Kernels here: a vertex pass (finiteness, vertex box, largest vertex norm),
-// a key pass (index check and the 63-bit Morton code of each centroid, 21
-// bits per axis, in the vertex box), a stable LSD radix sort of (u64 key, u32
-// value) pairs with 8-bit digits, and the scatter of triangles into leaf
-// order.
+// a key pass (index check and the Morton code of each centroid in the vertex
+// box, packed above the triangle's index into one u64), a one-sweep LSD radix
+// sort of those keys over the code bits, 8 bits per pass, and the scatter of
+// triangles into leaf order.
+//
+// Bits per axis: 4 more than a third of floor(log2 N) (rounded up), at most
+// 21 and at most what fits in 64 bits beside the index: about 2^4 cells per
+// axis for each triangle's share of the mesh, so two triangles rarely share a
+// cell (ties keep their input order, which is spatially coherent too) while
+// the sort runs only ceil(3 b / 8) passes (5 for 7.5M triangles instead of 8
+// for the full 63 bits).
 #include "internal.hpp"
 
 namespace gd {
@@ -35,35 +42,46 @@ __device__ __forceinline__ float wave_min_reduce(float v) {
   return v;
 }
 
-// Vertex pass.  vb: 7 ints (ordered floats): vertex box min xyz, max xyz,
-// and an upper bound of the largest vertex norm |x|.  flags: bit 1 = a
-// non-finite vertex.  One reduction per workgroup, one atomic per value.
+// Vertex pass.  Each workgroup reduces its share of the vertices to 8 ints
+// in part[8 * block]: vertex box min xyz, max xyz (ordered floats), an upper
+// bound of the largest vertex norm |x| (a non-negative float's bits), and the
+// non-finite flag (2).  A one-workgroup pass then reduces the partials into
+// vb[0..6] and flags (no atomics on a few hot addresses).
 constexpr int kVpThreads = 256;
 __global__ __launch_bounds__(kVpThreads) void k_vertex_pass(const float* __restrict__ v, uint32_t nv,
-                                                            int* __restrict__ vb, uint32_t* __restrict__ flags) {
+                                                            int* __restrict__ part) {
   float lo[3] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf()};
   float hi[3] = {-__builtin_huge_valf(), -__builtin_huge_valf(), -__builtin_huge_valf()};
-  float rmax = 0.f;
+  float r2max = 0.f;   // largest squared norm
   uint32_t bad = 0;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
-    const float x = v[3 * i], y = v[3 * i + 1], z = v[3 * i + 2];
-    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
-      bad = 2u;
-      continue;
-    }
+  // (a mesh with a non-finite vertex is rejected, so its box and norm do not matter)
+  auto take = [&](float x, float y, float z) {
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) bad = 2u;
     lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
     hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
-    rmax = fmaxf(rmax, sqrtf(x * x + y * y + z * z));
+    r2max = fmaxf(r2max, x * x + y * y + z * z);
+  };
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // four vertices (48 bytes) per thread and step, three 16-byte loads
+  const uint64_t ng = nv / 4u;
+  for (uint64_t g = t0; g < ng; g += stride) {
+    const __attribute__((address_space(1))) float* p = gptr(v) + 12ull * g;
+    const f4u a = gload<f4u>(p), b = gload<f4u>(p + 4), c = gload<f4u>(p + 8);
+    take(a.x, a.y, a.z);
+    take(a.w, b.x, b.y);
+    take(b.z, b.w, c.x);
+    take(c.y, c.z, c.w);
   }
-  // a few roundings of relative size 2^-24 each: widen by 2^-20
+  for (uint64_t i = 4u * ng + t0; i < nv; i += stride) take(v[3 * i], v[3 * i + 1], v[3 * i + 2]);
   float r[7];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     r[k] = wave_min_reduce(lo[k]);
     r[3 + k] = wave_max_reduce(hi[k]);
   }
-  r[6] = wave_max_reduce(rmax) * (1.0f + 0x1p-20f);
+  // a few roundings of relative size 2^-24 each: widen by 2^-20
+  r[6] = sqrtf(wave_max_reduce(r2max)) * (1.0f + 0x1p-20f);
   __shared__ float sr[kVpThreads / 64][7];
   __shared__ uint32_t s_bad;
   if (threadIdx.x == 0) s_bad = 0u;
@@ -78,19 +96,53 @@ __global__ __launch_bounds__(kVpThreads) void k_vertex_pass(const float* __restr
     const int k = threadIdx.x;
     float a = sr[0][k];
     for (int q = 1; q < kVpThreads / 64; ++q) a = k < 3 ? fminf(a, sr[q][k]) : fmaxf(a, sr[q][k]);
-    if (k < 3) atomicMin(&vb[k], ordered(a));
-    else atomicMax(&vb[k], ordered(a));
+    part[8ull * blockIdx.x + k] = ordered(a);
   }
-  if (threadIdx.x == 0 && s_bad) atomicOr(flags, s_bad);
+  if (threadIdx.x == 7) part[8ull * blockIdx.x + 7] = (int)s_bad;
 }
 
-__global__ void k_init_vb(int* vb, uint32_t* flags) {
-  if (threadIdx.x < 3) {
-    vb[threadIdx.x] = ordered(__builtin_huge_valf());
-    vb[3 + threadIdx.x] = ordered(-__builtin_huge_valf());
+__device__ __forceinline__ int wave_min_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// One workgroup: min of the partial minima, max of the maxima and norms, or
+// of the flags (the order-preserving int map keeps min and max).
+__global__ __launch_bounds__(kVpThreads) void k_vertex_final(const int* __restrict__ part, uint32_t nblocks,
+                                                             int* __restrict__ vb, uint32_t* __restrict__ flags) {
+  int a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = k < 3 ? INT_MAX : (k < 7 ? INT_MIN : 0);
+  for (uint32_t b = threadIdx.x; b < nblocks; b += kVpThreads) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int x = part[8ull * b + k];
+      a[k] = k < 3 ? min(a[k], x) : (k < 7 ? max(a[k], x) : (a[k] | x));
+    }
   }
-  if (threadIdx.x == 3) vb[6] = 0;
-  if (threadIdx.x == 0) *flags = 0;
+  __shared__ int sa[kVpThreads / 64][8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < 3) a[k] = wave_min_i(a[k]);
+    else if (k < 7) a[k] = wave_max_i(a[k]);
+    else for (int o = 32; o > 0; o >>= 1) a[k] |= __shfl_xor(a[k], o, 64);
+  }
+  const uint32_t w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0u)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sa[w][k] = a[k];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int k = threadIdx.x;
+    int x = sa[0][k];
+    for (int q = 1; q < kVpThreads / 64; ++q) x = k < 3 ? min(x, sa[q][k]) : (k < 7 ? max(x, sa[q][k]) : (x | sa[q][k]));
+    if (k < 7) vb[k] = x;
+    else *flags = (uint32_t)x;
+  }
 }
 
 // Spread the low 21 bits of x so that bit i lands at bit 3i.
@@ -105,9 +157,11 @@ __device__ __forceinline__ uint64_t spread3(uint64_t x) {
 }
 
 // Key pass, one thread per triangle: the index check (flags bit 0) and the
-// 63-bit Morton code of the FP32 centroid, normalised to the vertex box.
+// packed sort key of triangle t: the Morton code of its FP32 centroid,
+// normalised to the vertex box with `bits` bits per axis, shifted above the
+// index_bits low bits that hold t.
 __global__ void k_keys(const float* __restrict__ v, uint32_t nv, const uint32_t* __restrict__ f, uint32_t nt,
-                       const int* __restrict__ vb, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                       const int* __restrict__ vb, uint32_t bits, uint32_t index_bits, uint64_t* __restrict__ keys,
                        uint32_t* __restrict__ flags) {
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
@@ -116,225 +170,359 @@ __global__ void k_keys(const float* __restrict__ v, uint32_t nv, const uint32_t*
   if (i0 >= nv || i1 >= nv || i2 >= nv) {
     atomicOr(flags, 1u);
   } else {
+    const float cells = (float)(1u << bits);   // cells per axis
+    const uint32_t qmax = (1u << bits) - 1u;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const float lo = unordered(vb[k]), hi = unordered(vb[3 + k]);
       const float c = (v[3ull * i0 + k] + v[3ull * i1 + k] + v[3ull * i2 + k]) * (1.0f / 3.0f);
       const float ext = hi - lo;
       const float u = ext > 0.f ? (c - lo) / ext : 0.f;
-      const float sc = u * 2097152.0f;  // 2^21 cells per axis
-      const uint32_t q = sc <= 0.f ? 0u : (sc >= 2097151.0f ? 2097151u : (uint32_t)sc);
+      const float sc = u * cells;
+      const uint32_t q = sc <= 0.f ? 0u : (sc >= (float)qmax ? qmax : (uint32_t)sc);
       code |= spread3(q) << (2 - k);   // x on the highest of each bit triple
     }
   }
-  keys[t] = code;
-  vals[t] = (uint32_t)t;
+  keys[t] = (code << index_bits) | t;
 }
 
 // ---------------------------------------------------------------- radix sort
+// One-sweep LSD radix sort of the packed keys (Morton code above the triangle
+// index: every key is distinct, and sorting by the code bits alone, stably,
+// gives the order of the codes with ties in index order).  One kernel counts
+// the digits of every pass in a single read of the keys.  Each pass is then
+// one kernel: workgroup t ranks tile t's keys by digit in LDS, learns how many
+// keys with each digit the earlier tiles hold through a decoupled look-back
+// over the counts those tiles publish, and writes each key to its place.
+//
+// A workgroup waits only for tiles of lower index.  Workgroups reach the
+// compute units in index order within each XCD, so the unfinished tile of
+// lowest index is always resident (every workgroup of its XCD that was placed
+// before it has a lower index and has therefore finished) and never waits:
+// the waits end.  Every wait is also bounded: a timeout sets a flag that the
+// host reports as an error.  (No global ticket counter: one atomic per
+// workgroup on a single word serialises at tens of ns each.)
 constexpr int kRsThreads = 256;
 constexpr int kRsRowsPerWave = 16;
-constexpr int kRsTile = kRsThreads * kRsRowsPerWave;  // 4096 keys per block
+constexpr int kRsTile = kRsThreads * kRsRowsPerWave;  // 4096 keys per tile
+constexpr uint32_t kRsMaxPasses = 8;
+constexpr uint32_t kRsSpinLimit = 1u << 20;
+constexpr uint32_t kLookback = 16;   // look-back words read per round trip
 
-// hist[d * nblocks + b] = number of keys of block b with digit d
-__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t* __restrict__ keys, uint32_t n,
-                                                         uint32_t shift, uint32_t* __restrict__ hist,
-                                                         uint32_t nblocks) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  uint64_t base = (uint64_t)blockIdx.x * kRsTile;
-  for (int r = 0; r < kRsRowsPerWave; ++r) {
-    uint64_t i = base + (uint64_t)r * kRsThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
-  }
-  __syncthreads();
-  hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+struct SortCtl {                                // zeroed before the sort
+  uint32_t hist[kRsMaxPasses][256];             // keys per digit, per pass
+  uint32_t timeout;                             // a look-back wait gave up
+};
+constexpr size_t kSortCtlBytes = (sizeof(SortCtl) + 255) & ~size_t(255);
+
+// Look-back word of (tile, digit): high half = 2 (pass + 1) + inclusive, low
+// half = the tile's count of the digit (aggregate) or the count over tiles
+// 0..tile (inclusive).  A word with another pass in its tag is not yet written
+// for this pass.
+__device__ __forceinline__ uint64_t lb_word(uint32_t pass, bool incl, uint32_t v) {
+  return ((uint64_t)(2u * (pass + 1u) + (incl ? 1u : 0u)) << 32) | v;
 }
 
-// Exclusive scan of `len` counts in three launches: tile sums, a scan of the
-// tile sums, and the in-place rescan of each tile with its offset.
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
-constexpr uint64_t kScanTile = (uint64_t)kScanThreads * kScanItems;  // 4096 counts per workgroup
-
-// Exclusive scan of one value per thread across the workgroup; returns the
-// workgroup total.
-__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* s, uint32_t* excl) {
-  const uint32_t t = threadIdx.x;
-  s[t] = v;
-  __syncthreads();
-  for (uint32_t off = 1; off < kScanThreads; off <<= 1) {
-    uint32_t x = t >= off ? s[t - off] : 0u;
-    __syncthreads();
-    s[t] += x;
-    __syncthreads();
-  }
-  *excl = s[t] - v;
-  uint32_t total = s[kScanThreads - 1];
-  __syncthreads();
-  return total;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const uint32_t* __restrict__ a, uint64_t len,
-                                                             uint32_t* __restrict__ tile_sum) {
-  __shared__ uint32_t s[kScanThreads];
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-  uint32_t v = 0;
+// Lanes of the wave (among those with ok set) holding the same digit d.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool ok) {
+  uint64_t same = __ballot(ok);
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i)
-    if (base + i < len) v += a[base + i];
-  uint32_t excl;
-  uint32_t total = block_exclusive(v, s, &excl);
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
-}
-
-// One workgroup scans the tile sums in place (exclusive).
-__global__ __launch_bounds__(kScanThreads) void k_scan_sums(uint32_t* __restrict__ tile_sum, uint32_t n) {
-  __shared__ uint32_t s[kScanThreads];
-  uint32_t carry = 0;
-  for (uint32_t b = 0; b < n; b += kScanThreads) {
-    const uint32_t i = b + threadIdx.x;
-    uint32_t v = i < n ? tile_sum[i] : 0u, excl;
-    uint32_t total = block_exclusive(v, s, &excl);
-    if (i < n) tile_sum[i] = carry + excl;
-    carry += total;
+  for (int bit = 0; bit < 8; ++bit) {
+    const uint64_t m = __ballot((d >> bit) & 1u);
+    same &= ((d >> bit) & 1u) ? m : ~m;
   }
+  return same;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint32_t* __restrict__ a, uint64_t len,
-                                                             const uint32_t* __restrict__ tile_sum) {
-  __shared__ uint32_t s[kScanThreads];
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems], sum = 0;
+// Exclusive scan of one value per thread across the 256-thread workgroup
+// (wave scans, then the four wave totals); *total = the workgroup's sum.
+// s4: 4 words of LDS.
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* s4, uint32_t* total) {
+  const uint32_t lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  uint32_t x = v;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    v[i] = base + i < len ? a[base + i] : 0u;
-    sum += v[i];
+  for (uint32_t off = 1; off < kWave; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, kWave);
+    if (lane >= off) x += y;
   }
-  uint32_t excl;
-  block_exclusive(sum, s, &excl);
-  uint32_t run = tile_sum[blockIdx.x] + excl;
+  if (lane == kWave - 1) s4[w] = x;
+  __syncthreads();
+  uint32_t pre = 0, all = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < len) a[base + i] = run;
-    run += v[i];
+  for (uint32_t q = 0; q < kRsThreads / kWave; ++q) {
+    const uint32_t t = s4[q];
+    pre += q < w ? t : 0u;
+    all += t;
   }
+  __syncthreads();
+  *total = all;
+  return pre + x - v;
 }
 
-// Stable scatter.  Wave w of the block ranks rows w*16 .. w*16+15 of the
-// block's tile (a row = 64 consecutive keys) in order: lanes holding the same
+// Digit counts of all passes: each wave takes 8 rows of 64 keys at a time
+// (their loads issued together) and adds each key's digit of each pass to the
+// workgroup's LDS histogram (LDS atomics; a row whose keys share the digit
+// adds once), which is then stored whole as the workgroup's row of `part`
+// (passes x 256 counts).  k_sort_hist_sum adds the rows up: a few thousand
+// global atomic adds to distinct words, instead of one per bin and workgroup.
+constexpr uint32_t kHistRows = 8;
+constexpr uint32_t kHistMaxBlocks = 1024;
+constexpr uint32_t kHistSumRows = 32;    // partial rows per thread of the sum
+__global__ __launch_bounds__(kRsThreads) void k_sort_hist(const uint64_t* __restrict__ keys, uint32_t n,
+                                                           uint32_t lo_bit, uint32_t passes,
+                                                           uint32_t* __restrict__ part) {
+  __shared__ uint32_t h[kRsMaxPasses][256];
+  for (uint32_t i = threadIdx.x; i < kRsMaxPasses * 256; i += kRsThreads) (&h[0][0])[i] = 0u;
+  __syncthreads();
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint64_t rows = ((uint64_t)n + kWave - 1) / kWave;
+  const uint64_t waves = (uint64_t)gridDim.x * (kRsThreads / kWave);
+  for (uint64_t r0 = ((uint64_t)blockIdx.x * (kRsThreads / kWave) + threadIdx.x / kWave) * kHistRows; r0 < rows;
+       r0 += waves * kHistRows) {
+    uint64_t k[kHistRows];
+#pragma unroll
+    for (uint32_t j = 0; j < kHistRows; ++j) {
+      const uint64_t i = (r0 + j) * kWave + lane;
+      k[j] = i < n ? keys[i] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kHistRows; ++j) {
+      if (r0 + j >= rows) break;   // uniform across the wave
+      const bool ok = (r0 + j) * kWave + lane < n;
+      const uint64_t live = __ballot(ok);
+      for (uint32_t p = 0; p < passes; ++p) {
+        const uint32_t d = (uint32_t)(k[j] >> (lo_bit + 8u * p)) & 255u;
+        // a row whose live keys share one digit (common for the high digits
+        // of a spatially coherent input) costs one add
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        if (__ballot(ok && d == d0) == live) {
+          if (lane == 0) atomicAdd(&h[p][d0], (uint32_t)__popcll(live));
+        } else if (ok) {
+          atomicAdd(&h[p][d], 1u);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  uint32_t* row = part + (uint64_t)blockIdx.x * passes * 256u;
+  for (uint32_t i = threadIdx.x; i < passes * 256u; i += kRsThreads) row[i] = (&h[0][0])[i];
+}
+
+// Workgroup (p, c): thread d adds digit d of pass p over partial rows
+// c*32 .. c*32+31, then one global add.
+__global__ __launch_bounds__(kRsThreads) void k_sort_hist_sum(const uint32_t* __restrict__ part, uint32_t rows,
+                                                               uint32_t passes, SortCtl* ctl) {
+  const uint32_t p = blockIdx.x, d = threadIdx.x;
+  const uint32_t r0 = blockIdx.y * kHistSumRows;
+  uint32_t sum = 0;
+#pragma unroll
+  for (uint32_t r = 0; r < kHistSumRows; ++r)
+    if (r0 + r < rows) sum += part[((uint64_t)(r0 + r) * passes + p) * 256u + d];
+  if (sum) atomicAdd(&ctl->hist[p][d], sum);
+}
+
+// One pass over the digit at bit `shift`.  Wave w ranks rows w*16 .. w*16+15
+// of the tile (a row = 64 consecutive keys) in order: lanes holding the same
 // digit are found with eight ballots, their order inside the row comes from
-// mbcnt, and a per-wave running count per digit carries the order across
-// rows.  A per-digit prefix over the four waves and an exclusive scan over the
-// 256 digits give each key its place in the tile sorted by digit; the tile is
-// reordered in LDS, and thread t then writes tile positions t, t + 256, ...
-// to the digit's global offset for this block plus the position inside the
-// digit's run, so consecutive threads store consecutive addresses of one run.
-__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
-                                                            const uint32_t* __restrict__ vin,
-                                                            uint64_t* __restrict__ kout,
-                                                            uint32_t* __restrict__ vout, uint32_t n,
-                                                            uint32_t shift, const uint32_t* __restrict__ offs,
-                                                            uint32_t nblocks) {
+// the lane mask below them, and a per-wave running count per digit carries
+// the order across rows.  A per-digit prefix over the four waves and an
+// exclusive scan over the 256 digits give each key its place in the tile
+// sorted by digit; the tile is reordered in LDS, and thread t then writes
+// tile positions t, t + 256, ... to the digit's global start, plus the keys
+// with that digit in earlier tiles, plus the position inside the digit's run,
+// so consecutive threads store consecutive addresses of one run.
+__global__ __launch_bounds__(kRsThreads) void k_sort_pass(const uint64_t* __restrict__ kin,
+                                                           uint64_t* __restrict__ kout, uint32_t n, uint32_t shift,
+                                                           uint32_t pass, SortCtl* ctl, uint64_t* lb) {
   __shared__ uint32_t wc[kRsThreads / kWave][257];
   __shared__ uint32_t lstart[256];
-  __shared__ uint32_t scan_s[kScanThreads];
+  __shared__ uint32_t gbase[256];
+  __shared__ uint32_t scan_s[kRsThreads / kWave];
   __shared__ uint64_t tk[kRsTile];
-  __shared__ uint32_t tv[kRsTile];
   const uint32_t w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   for (uint32_t i = threadIdx.x; i < (kRsThreads / kWave) * 257; i += kRsThreads) (&wc[0][0])[i] = 0;
   __syncthreads();
+  const uint32_t tile = blockIdx.x;
   uint64_t key[kRsRowsPerWave];
-  uint32_t val[kRsRowsPerWave], dig[kRsRowsPerWave], rk[kRsRowsPerWave];
-  const uint64_t base = (uint64_t)blockIdx.x * kRsTile + (uint64_t)w * kRsRowsPerWave * kWave;
+  uint32_t dig[kRsRowsPerWave], rk[kRsRowsPerWave];
+  const uint64_t base = (uint64_t)tile * kRsTile + (uint64_t)w * kRsRowsPerWave * kWave;
   const uint64_t lt = (1ull << lane) - 1ull;
 #pragma unroll
   for (int r = 0; r < kRsRowsPerWave; ++r) {
-    uint64_t i = base + (uint64_t)r * kWave + lane;
-    bool ok = i < n;
-    key[r] = ok ? kin[i] : 0ull;
-    val[r] = ok ? vin[i] : 0u;
-    uint32_t d = ok ? (uint32_t)((key[r] >> shift) & 255u) : 256u;
-    dig[r] = d;
-    uint64_t same = __ballot(ok);
+    const uint64_t i = base + (uint64_t)r * kWave + lane;
+    key[r] = i < n ? kin[i] : 0ull;
+  }
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-      uint64_t m = __ballot((d >> bit) & 1u);
-      same &= ((d >> bit) & 1u) ? m : ~m;
-    }
-    uint32_t prev = ok ? wc[w][d] : 0u;
+  for (int r = 0; r < kRsRowsPerWave; ++r) {
+    const bool ok = base + (uint64_t)r * kWave + lane < n;
+    const uint32_t d = ok ? (uint32_t)((key[r] >> shift) & 255u) : 256u;
+    dig[r] = d;
+    const uint64_t same = digit_peers(d, ok);
+    const uint32_t prev = ok ? wc[w][d] : 0u;
     rk[r] = prev + (uint32_t)__popcll(same & lt);
     // lowest lane of each digit group advances that digit's running count
     if (ok && (same & lt) == 0ull) wc[w][d] = prev + (uint32_t)__popcll(same);
   }
   __syncthreads();
-  {
-    // per digit: the four waves' offsets inside the digit's run, and the
-    // run's start in the digit-sorted tile
-    const uint32_t d = threadIdx.x;  // 256 threads, one per digit
-    uint32_t run = 0;
+  const uint32_t d = threadIdx.x;  // 256 threads, one per digit
+  uint32_t run = 0;
 #pragma unroll
-    for (int q = 0; q < kRsThreads / kWave; ++q) {
-      uint32_t c = wc[q][d];
-      wc[q][d] = run;
-      run += c;
-    }
-    uint32_t excl;
-    block_exclusive(run, scan_s, &excl);
-    lstart[d] = excl;
+  for (int q = 0; q < kRsThreads / kWave; ++q) {
+    const uint32_t c = wc[q][d];
+    wc[q][d] = run;
+    run += c;
   }
-  __syncthreads();
+  // publish this tile's count of digit d (tile 0: already the inclusive count)
+  uint64_t* const my = lb + (uint64_t)tile * 256u + d;
+  __hip_atomic_store(my, lb_word(pass, tile == 0u, run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t total;
+  lstart[d] = block_exclusive(run, scan_s, &total);
+  const uint32_t gstart = block_exclusive(ctl->hist[pass][d], scan_s, &total);
 #pragma unroll
   for (int r = 0; r < kRsRowsPerWave; ++r) {
-    if (dig[r] < 256u) {
-      const uint32_t lp = lstart[dig[r]] + wc[w][dig[r]] + rk[r];
-      tk[lp] = key[r];
-      tv[lp] = val[r];
-    }
+    if (dig[r] < 256u) tk[lstart[dig[r]] + wc[w][dig[r]] + rk[r]] = key[r];
   }
+  // look back over the earlier tiles' counts of digit d, kLookback tiles per
+  // round trip: add published counts from the nearest tile down, up to and
+  // including the first inclusive one; an unpublished tile ends the window
+  // and is read again.
+  uint32_t before = 0;
+  if (tile > 0u) {
+    uint32_t j = tile, spins = 0;   // tiles below j are still to be added
+    for (;;) {
+      uint64_t wd[kLookback];
+#pragma unroll
+      for (uint32_t q = 0; q < kLookback; ++q)
+        wd[q] = q < j ? __hip_atomic_load(lb + (uint64_t)(j - 1u - q) * 256u + d, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT)
+                      : 0ull;
+      bool done = false;
+      uint32_t used = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < kLookback; ++q) {
+        if (done || used != q || q >= j) continue;
+        const uint32_t tag = (uint32_t)(wd[q] >> 32);
+        if ((tag >> 1) != pass + 1u) continue;    // not yet published: stop the window here
+        before += (uint32_t)wd[q];
+        used = q + 1u;
+        done = (tag & 1u) != 0u;
+      }
+      j -= used;
+      if (done || j == 0u) break;
+      if (used == 0u) {
+        if (++spins > kRsSpinLimit) {
+          __hip_atomic_store(&ctl->timeout, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __hip_atomic_store(my, lb_word(pass, true, before + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  gbase[d] = gstart + before - lstart[d];
   __syncthreads();
-  const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
+  const uint64_t tile0 = (uint64_t)tile * kRsTile;
   const uint32_t valid = n - tile0 < (uint64_t)kRsTile ? (uint32_t)(n - tile0) : (uint32_t)kRsTile;
   for (uint32_t i = threadIdx.x; i < valid; i += kRsThreads) {
     const uint64_t k = tk[i];
-    const uint32_t d = (uint32_t)((k >> shift) & 255u);
-    const uint32_t pos = offs[(uint64_t)d * nblocks + blockIdx.x] + (i - lstart[d]);
-    kout[pos] = k;
-    vout[pos] = tv[i];
+    const uint32_t pos = gbase[(uint32_t)(k >> shift) & 255u] + i;
+    if (pos < n) kout[pos] = k;   // always, unless a look-back wait timed out
   }
 }
 
-// Triangles in sorted (= leaf) order, plus the caller index of each.
-// The 256 triangles of a workgroup are gathered into LDS, then written out
-// as one contiguous block (9,216 bytes at a 16-byte aligned offset) with
-// 16-byte stores.
-constexpr int kEmitThreads = 256;
-__global__ __launch_bounds__(kEmitThreads) void k_emit(const float* __restrict__ v, const uint32_t* __restrict__ f,
-                                                       uint32_t nt, const uint32_t* __restrict__ sorted,
-                                                       float* __restrict__ tris, uint32_t* __restrict__ orig,
-                                                       uint32_t* __restrict__ fl) {
-  __shared__ __align__(16) float st[9 * kEmitThreads];
-  const uint64_t s0 = (uint64_t)blockIdx.x * kEmitThreads;
-  const uint64_t s = s0 + threadIdx.x;
-  if (s < nt) {
-    const uint32_t o = sorted[s];
-    orig[s] = o;
+// Tree of a new mesh (identity pose).  Workgroup blk owns leaves
+// [blk S, blk S + S) of the L = 2^D leaves, S = min(L, 512): leaf j holds the
+// key-order triangles [floor(j n / L), floor((j + 1) n / L)) (1 or 2), so the
+// workgroup's leaves hold one run of at most 2S triangles.  It gathers them
+// (sorted key -> caller index -> vertex indices -> vertices) into LDS, writes
+// them out as one contiguous run with 16-byte stores, computes its leaf boxes
+// from LDS and reduces its subtree there, writing every node once.  The
+// upper levels follow in k_reduce_levels.
+constexpr int kTreeThreads = 512;
+__global__ __launch_bounds__(kTreeThreads) void k_emit_tree(const float* __restrict__ v, uint32_t nv,
+                                                            const uint32_t* __restrict__ f, uint32_t nt,
+                                                            const uint64_t* __restrict__ sorted, uint64_t index_mask,
+                                                            uint32_t L, uint32_t S, float* __restrict__ tris,
+                                                            uint32_t* __restrict__ orig, uint32_t* __restrict__ fl,
+                                                            float* __restrict__ boxes) {
+  __shared__ __align__(16) float st[18 * kTreeThreads];
+  __shared__ Box lb[kTreeThreads];
+  const uint32_t D = 31u - (uint32_t)__clz(L);
+  const uint32_t blk = blockIdx.x;
+  const uint32_t t0 = (uint32_t)(((uint64_t)blk * S * nt) >> D);
+  const uint32_t t1 = (uint32_t)(((uint64_t)(blk * S + S) * nt) >> D);
+  const uint32_t cnt = t1 - t0;   // <= 2 S
+  for (uint32_t i = threadIdx.x; i < cnt; i += kTreeThreads) {
+    const uint64_t sp = (uint64_t)t0 + i;
+    uint32_t o = (uint32_t)(sorted[sp] & index_mask);
+    if (o >= nt) o = nt - 1u;   // only after a sort timeout, which rejects the mesh
+    orig[sp] = o;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const uint32_t vi = f[3ull * o + c];
-      if (fl) fl[3ull * s + c] = vi;
+      if (fl) fl[3ull * sp + c] = vi;
+      const uint32_t vr = vi < nv ? vi : nv - 1u;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) st[9 * threadIdx.x + 3 * c + k] = v[3ull * vi + k];
+      for (int k = 0; k < 3; ++k) st[9 * i + 3 * c + k] = v[3ull * vr + k];
     }
   }
   __syncthreads();
-  const uint32_t cnt = nt - s0 < (uint64_t)kEmitThreads ? (uint32_t)(nt - s0) : (uint32_t)kEmitThreads;
-  const uint32_t nf = 9u * cnt, n4 = nf >> 2;
-  float* out = tris + 9ull * s0;     // 36 * 256 * blockIdx.x bytes: 16-byte aligned
-  for (uint32_t i = threadIdx.x; i < n4; i += kEmitThreads)
-    *reinterpret_cast<f4v*>(out + 4u * i) = *reinterpret_cast<const f4v*>(st + 4u * i);
-  for (uint32_t i = 4u * n4 + threadIdx.x; i < nf; i += kEmitThreads) out[i] = st[i];
+  // the run starts at float 9 t0 of a 16-byte aligned array: a scalar head
+  // up to the next 16-byte boundary, 16-byte stores, a scalar tail
+  const uint32_t nf = 9u * cnt;
+  float* out = tris + 9ull * t0;
+  uint32_t head = (4u - (uint32_t)((9ull * t0) & 3ull)) & 3u;
+  if (head > nf) head = nf;
+  const uint32_t n4 = (nf - head) >> 2;
+  if (threadIdx.x < head) out[threadIdx.x] = st[threadIdx.x];
+  for (uint32_t i = threadIdx.x; i < n4; i += kTreeThreads) {
+    const uint32_t q = head + 4u * i;
+    f4v x;
+    x.x = st[q];
+    x.y = st[q + 1];
+    x.z = st[q + 2];
+    x.w = st[q + 3];
+    *reinterpret_cast<f4v*>(out + q) = x;
+  }
+  for (uint32_t i = head + 4u * n4 + threadIdx.x; i < nf; i += kTreeThreads) out[i] = st[i];
+  // leaf boxes (the identity pose: the vertices themselves)
+  const uint32_t j = threadIdx.x;
+  if (j < S) {
+    Box b;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      b.lo[k] = __builtin_huge_valf();
+      b.hi[k] = -__builtin_huge_valf();
+    }
+    const uint32_t leaf = blk * S + j;
+    const uint32_t start = (uint32_t)(((uint64_t)leaf * nt) >> D);
+    const uint32_t end = (uint32_t)(((uint64_t)(leaf + 1) * nt) >> D);
+    for (uint32_t p = start; p < end; ++p) {
+      const float* q = st + 9u * (p - t0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          b.lo[k] = fminf(b.lo[k], q[3 * c + k]);
+          b.hi[k] = fmaxf(b.hi[k], q[3 * c + k]);
+        }
+    }
+    store_box(boxes, L + leaf, b);
+    lb[j] = b;
+  }
+  uint32_t base = L + blk * S;
+  for (uint32_t c = S; c > 1; c >>= 1) {
+    __syncthreads();
+    Box nb;
+    const bool act = j < c / 2;
+    if (act) nb = box_union(lb[2 * j], lb[2 * j + 1]);
+    __syncthreads();
+    base >>= 1;
+    if (act) {
+      lb[j] = nb;
+      store_box(boxes, base + j, nb);
+    }
+  }
 }
 
 // Deformable meshes: the triangles, in the leaf order of the original build,
@@ -353,52 +541,86 @@ __global__ void k_gather_tris(const float* __restrict__ v, const uint32_t* __res
 }
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_vertex_pass(const float* v, uint32_t nv, int* vb, uint32_t* flags, hipStream_t s) {
-  k_init_vb<<<1, 64, 0, s>>>(vb, flags);
-  uint32_t blocks = (uint32_t)(((uint64_t)nv + kVpThreads - 1) / kVpThreads);
-  if (blocks > 2048) blocks = 2048;
+constexpr uint32_t kVpMaxBlocks = 1024;
+
+size_t vertex_pass_scratch_bytes() { return (size_t)kVpMaxBlocks * 8u * sizeof(int); }
+
+hipError_t launch_vertex_pass(const float* v, uint32_t nv, int* vb, uint32_t* flags, int* part, hipStream_t s) {
+  uint32_t blocks = (uint32_t)(((uint64_t)nv / 4u + kVpThreads - 1) / kVpThreads);
+  if (blocks > kVpMaxBlocks) blocks = kVpMaxBlocks;
   if (blocks == 0) blocks = 1;
-  k_vertex_pass<<<blocks, kVpThreads, 0, s>>>(v, nv, vb, flags);
+  k_vertex_pass<<<blocks, kVpThreads, 0, s>>>(v, nv, part);
+  k_vertex_final<<<1, kVpThreads, 0, s>>>(part, blocks, vb, flags);
   return hipGetLastError();
+}
+
+KeyLayout key_layout(uint32_t nt) {
+  uint32_t d = 0;
+  while (d < 31u && (2u << d) <= nt) ++d;   // floor(log2 nt)
+  uint32_t ib = 0;
+  while (ib < 32u && (1ull << ib) < nt) ++ib;   // bits of the largest index nt - 1
+  uint32_t b = (d + 2u) / 3u + 4u;
+  if (b > 21u) b = 21u;
+  if (3u * b + ib > 64u) b = (64u - ib) / 3u;
+  return KeyLayout{ib, b};
 }
 
 hipError_t launch_keys(const float* v, uint32_t nv, const uint32_t* f, uint32_t nt, const int* vb, uint64_t* keys,
-                       uint32_t* vals, uint32_t* flags, hipStream_t s) {
-  k_keys<<<(nt + 255) / 256, 256, 0, s>>>(v, nv, f, nt, vb, keys, vals, flags);
+                       uint32_t* flags, hipStream_t s) {
+  const KeyLayout kl = key_layout(nt);
+  k_keys<<<(nt + 255) / 256, 256, 0, s>>>(v, nv, f, nt, vb, kl.axis_bits, kl.index_bits, keys, flags);
   return hipGetLastError();
 }
 
-// histogram words plus the scan's tile sums
-size_t radix_hist_words(uint32_t n) {
-  uint64_t h = (uint64_t)256 * ((n + kRsTile - 1) / kRsTile);
-  return (size_t)(h + (h + kScanTile - 1) / kScanTile);
+static uint32_t hist_blocks(uint32_t n) {
+  const uint32_t tiles = (uint32_t)(((uint64_t)n + kRsTile - 1) / kRsTile);
+  return tiles < kHistMaxBlocks ? tiles : kHistMaxBlocks;
 }
 
-hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
-                             uint32_t n, uint32_t* hist, hipStream_t s, int* result_in_tmp) {
-  uint32_t nblocks = (n + kRsTile - 1) / kRsTile;
-  const uint64_t hlen = (uint64_t)256 * nblocks;
-  const uint32_t tiles = (uint32_t)((hlen + kScanTile - 1) / kScanTile);
-  uint32_t* tile_sum = hist + hlen;
+// SortCtl, the look-back words (one per tile and digit), the histogram
+// partials (one row of up to 8 x 256 counts per histogram workgroup)
+size_t sort_workspace_bytes(uint32_t n) {
+  const uint64_t tiles = ((uint64_t)n + kRsTile - 1) / kRsTile;
+  return kSortCtlBytes + (size_t)tiles * 256u * sizeof(uint64_t) +
+         (size_t)hist_blocks(n) * kRsMaxPasses * 256u * sizeof(uint32_t);
+}
+
+const uint32_t* sort_timeout_flag(const void* ws) { return &reinterpret_cast<const SortCtl*>(ws)->timeout; }
+
+hipError_t launch_sort(uint64_t* keys, uint64_t* keys_tmp, uint32_t n, uint32_t lo_bit, uint32_t nbits, void* ws,
+                       hipStream_t s, int* result_in_tmp) {
+  const uint32_t passes = (nbits + 7u) / 8u;
+  if (n == 0 || passes == 0 || passes > kRsMaxPasses || lo_bit + nbits > 64u) return hipErrorInvalidValue;
+  const uint32_t tiles = (uint32_t)(((uint64_t)n + kRsTile - 1) / kRsTile);
+  SortCtl* ctl = reinterpret_cast<SortCtl*>(ws);
+  uint64_t* lb = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(ws) + kSortCtlBytes);
+  uint32_t* part = reinterpret_cast<uint32_t*>(lb + (uint64_t)tiles * 256u);
+  // the partial rows are written whole before they are read: clear the rest
+  hipError_t e = hipMemsetAsync(ws, 0, kSortCtlBytes + (size_t)tiles * 256u * sizeof(uint64_t), s);
+  if (e != hipSuccess) return e;
+  const uint32_t hb = hist_blocks(n);
+  k_sort_hist<<<hb, kRsThreads, 0, s>>>(keys, n, lo_bit, passes, part);
+  k_sort_hist_sum<<<dim3(passes, (hb + kHistSumRows - 1) / kHistSumRows), kRsThreads, 0, s>>>(part, hb, passes, ctl);
   uint64_t *ki = keys, *ko = keys_tmp;
-  uint32_t *vi = vals, *vo = vals_tmp;
-  for (uint32_t shift = 0; shift < 64; shift += 8) {
-    k_rs_hist<<<nblocks, kRsThreads, 0, s>>>(ki, n, shift, hist, nblocks);
-    k_scan_tiles<<<tiles, kScanThreads, 0, s>>>(hist, hlen, tile_sum);
-    k_scan_sums<<<1, kScanThreads, 0, s>>>(tile_sum, tiles);
-    k_scan_apply<<<tiles, kScanThreads, 0, s>>>(hist, hlen, tile_sum);
-    k_rs_scatter<<<nblocks, kRsThreads, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nblocks);
-    uint64_t* tk = ki; ki = ko; ko = tk;
-    uint32_t* tv = vi; vi = vo; vo = tv;
+  for (uint32_t p = 0; p < passes; ++p) {
+    k_sort_pass<<<tiles, kRsThreads, 0, s>>>(ki, ko, n, lo_bit + 8u * p, p, ctl, lb);
+    uint64_t* t = ki;
+    ki = ko;
+    ko = t;
   }
   *result_in_tmp = (ki == keys_tmp);
   return hipGetLastError();
 }
 
-hipError_t launch_emit(const float* v, const uint32_t* f, uint32_t nt, const uint32_t* sorted, float* tris,
-                       uint32_t* orig, uint32_t* fl, hipStream_t s) {
-  k_emit<<<(nt + kEmitThreads - 1) / kEmitThreads, kEmitThreads, 0, s>>>(v, f, nt, sorted, tris, orig, fl);
-  return hipGetLastError();
+hipError_t launch_emit_tree(const float* v, uint32_t nv, const uint32_t* f, uint32_t nt, const uint64_t* sorted,
+                            uint32_t index_bits, uint32_t L, float* tris, uint32_t* orig, uint32_t* fl, float* boxes,
+                            hipStream_t s) {
+  const uint64_t mask = index_bits >= 64u ? ~0ull : (1ull << index_bits) - 1ull;
+  const uint32_t S = L < (uint32_t)kTreeThreads ? L : (uint32_t)kTreeThreads;
+  k_emit_tree<<<L / S, kTreeThreads, 0, s>>>(v, nv, f, nt, sorted, mask, L, S, tris, orig, fl, boxes);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_upper(boxes, L / S, s);
 }
 
 hipError_t launch_gather_tris(const float* v, const uint32_t* fl, uint32_t nt, float* tris, hipStream_t s) {

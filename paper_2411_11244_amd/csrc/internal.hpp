@@ -148,24 +148,47 @@ struct StepHead {
 };
 
 // build.hip
-// vb: 7 ints (vertex box as ordered floats, largest vertex norm); flags bit 1 =
-// a non-finite vertex.
-hipError_t launch_vertex_pass(const float* v, uint32_t nv, int* vb, uint32_t* flags, hipStream_t s);
-// keys/vals of every triangle (Morton code in the vertex box, iota); flags bit
-// 0 = a vertex index >= nv.  Needs vb from launch_vertex_pass.
+// Vertex pass: vb = 7 ints (vertex box as ordered floats, largest vertex norm);
+// flags = 2 if a vertex is not finite, else 0.  part: vertex_pass_scratch_bytes()
+// of device scratch.
+size_t vertex_pass_scratch_bytes();
+hipError_t launch_vertex_pass(const float* v, uint32_t nv, int* vb, uint32_t* flags, int* part, hipStream_t s);
+// Sort key of a mesh of nt triangles: Morton code (axis_bits per axis) above
+// index_bits bits of triangle index, 3 axis_bits + index_bits <= 64.
+struct KeyLayout {
+  uint32_t index_bits, axis_bits;
+};
+KeyLayout key_layout(uint32_t nt);
+// Packed key of every triangle; flags bit 0 = a vertex index >= nv.  Needs vb
+// from launch_vertex_pass.
 hipError_t launch_keys(const float* v, uint32_t nv, const uint32_t* f, uint32_t nt, const int* vb, uint64_t* keys,
-                       uint32_t* vals, uint32_t* flags, hipStream_t s);
-size_t radix_hist_words(uint32_t n);
-hipError_t launch_radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, uint32_t n,
-                             uint32_t* hist, hipStream_t s, int* result_in_tmp);
-hipError_t launch_emit(const float* v, const uint32_t* f, uint32_t nt, const uint32_t* sorted, float* tris,
-                       uint32_t* orig, uint32_t* fl, hipStream_t s);
+                       uint32_t* flags, hipStream_t s);
+// One-sweep LSD sort of n distinct u64 keys by bits [lo_bit, lo_bit + nbits),
+// 8 bits per pass, ping-pong between the two buffers (*result_in_tmp says which
+// holds the result).  ws: sort_workspace_bytes(n) of device memory (cleared
+// here); after the stream reaches the end of the sort, *sort_timeout_flag(ws)
+// is nonzero if a look-back wait gave up (the order is then invalid).
+size_t sort_workspace_bytes(uint32_t n);
+const uint32_t* sort_timeout_flag(const void* ws);
+hipError_t launch_sort(uint64_t* keys, uint64_t* keys_tmp, uint32_t n, uint32_t lo_bit, uint32_t nbits, void* ws,
+                       hipStream_t s, int* result_in_tmp);
+// The tree of a new mesh from its sorted keys: triangles in key order (index =
+// the low index_bits bits of each key), their caller indices, their vertex
+// index triples if fl is set, and every node box (L = 2^floor(log2 nt)
+// leaves).  Vertex indices are clamped to nv - 1 for the reads (a mesh with a
+// larger one is rejected by the key pass's flag).
+hipError_t launch_emit_tree(const float* v, uint32_t nv, const uint32_t* f, uint32_t nt, const uint64_t* sorted,
+                            uint32_t index_bits, uint32_t L, float* tris, uint32_t* orig, uint32_t* fl, float* boxes,
+                            hipStream_t s);
 // Deformable meshes: triangles (leaf order) gathered from new vertices through
 // the leaf-order index triples fl that launch_emit wrote.
 hipError_t launch_gather_tris(const float* v, const uint32_t* fl, uint32_t nt, float* tris, hipStream_t s);
 
 // refit.hip
 hipError_t launch_refit(const float* tris, uint32_t n, uint32_t L, const Xf32& T, float* boxes, hipStream_t s);
+// Upper levels of a tree whose level of `count` nodes (ids count .. 2 count - 1)
+// is already written.
+hipError_t launch_reduce_upper(float* boxes, uint32_t count, hipStream_t s);
 
 // One tree of a batched refit: its triangles (leaf order), its output boxes,
 // the transform; S and first_block are filled by the planner.

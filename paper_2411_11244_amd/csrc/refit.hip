@@ -245,16 +245,20 @@ hipError_t launch_refit_batch(const RefitPlan& plan, const void* dev, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_refit(const float* tris, uint32_t n, uint32_t L, const Xf32& T, float* boxes, hipStream_t s) {
-  uint32_t S = L < (uint32_t)kRefitThreads ? L : (uint32_t)kRefitThreads;
-  k_refit_leaves<<<L / S, kRefitThreads, 0, s>>>(tris, n, L, T, boxes, S);
-  uint32_t count = L / S;  // nodes of the level holding the subtree roots
+hipError_t launch_reduce_upper(float* boxes, uint32_t count, hipStream_t s) {
   while (count > 1) {
     uint32_t S2 = count < (uint32_t)kRefitThreads ? count : (uint32_t)kRefitThreads;
     k_reduce_levels<<<count / S2, kRefitThreads, 0, s>>>(boxes, count, S2);
     count /= S2;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_refit(const float* tris, uint32_t n, uint32_t L, const Xf32& T, float* boxes, hipStream_t s) {
+  uint32_t S = L < (uint32_t)kRefitThreads ? L : (uint32_t)kRefitThreads;
+  k_refit_leaves<<<L / S, kRefitThreads, 0, s>>>(tris, n, L, T, boxes, S);
+  // the level holding the subtree roots has L / S nodes
+  return launch_reduce_upper(boxes, L / S, s);
 }
 
 }  // namespace gd

@@ -57,19 +57,29 @@ def test_tri_tri_vs_oracle(orc, gctx, mode):
     assert np.all(np.abs(d32 - ref) <= 64 * 2.0 ** -24 * (1 + scale)), np.abs(d32 - ref).max()
 
 
+def morton_bits(n):
+    """Bits per axis: 4 more than ceil(floor(log2 n) / 3), at most 21 and at
+    most what fits in a 64-bit key beside the index bits of n - 1."""
+    b = min(21, (int(np.floor(np.log2(n))) + 2) // 3 + 4)
+    index_bits = int(n - 1).bit_length()
+    return min(b, (64 - index_bits) // 3)
+
+
 def numpy_morton_order(mesh):
-    """Leaf order from the definition: 21-bit-per-axis Morton code of the FP32
-    centroid in the box of all vertices, stable sort."""
+    """Leaf order from the definition: Morton code of the FP32 centroid in the
+    box of all vertices, morton_bits(n) bits per axis, stable sort."""
     v = mesh.verts
     t = mesh.tris
+    b = morton_bits(len(t))
     c = (v[t[:, 0]] + v[t[:, 1]] + v[t[:, 2]]) * np.float32(1.0 / 3.0)
     lo, hi = v.min(0), v.max(0)
     ext = hi - lo
     u = np.where(ext > 0, (c - lo) / np.where(ext > 0, ext, 1), 0).astype(np.float32)
-    s = u * np.float32(2097152.0)
-    q = np.where(s <= 0, 0, np.where(s >= 2097151.0, 2097151, np.floor(s))).astype(np.uint64)
+    s = u * np.float32(2.0 ** b)
+    qmax = 2 ** b - 1
+    q = np.where(s <= 0, 0, np.where(s >= np.float32(qmax), qmax, np.floor(s))).astype(np.uint64)
     code = np.zeros(len(t), np.uint64)
-    for bit in range(21):
+    for bit in range(b):
         for k in range(3):
             code |= ((q[:, k] >> np.uint64(bit)) & np.uint64(1)) << np.uint64(3 * bit + (2 - k))
     return np.argsort(code, kind="stable")
