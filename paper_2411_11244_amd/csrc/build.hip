@@ -165,17 +165,18 @@ __global__ void k_keys(const float* __restrict__ v, uint32_t nv, const uint32_t*
                        uint32_t* __restrict__ flags) {
   const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
-  const uint32_t i0 = f[3 * t], i1 = f[3 * t + 1], i2 = f[3 * t + 2];
+  const u3u fi = gload3<u3u>(f, t);
   uint64_t code = 0;
-  if (i0 >= nv || i1 >= nv || i2 >= nv) {
+  if (fi.x >= nv || fi.y >= nv || fi.z >= nv) {
     atomicOr(flags, 1u);
   } else {
+    const f3u p0 = gload3<f3u>(v, fi.x), p1 = gload3<f3u>(v, fi.y), p2 = gload3<f3u>(v, fi.z);
     const float cells = (float)(1u << bits);   // cells per axis
     const uint32_t qmax = (1u << bits) - 1u;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const float lo = unordered(vb[k]), hi = unordered(vb[3 + k]);
-      const float c = (v[3ull * i0 + k] + v[3ull * i1 + k] + v[3ull * i2 + k]) * (1.0f / 3.0f);
+      const float c = (p0[k] + p1[k] + p2[k]) * (1.0f / 3.0f);
       const float ext = hi - lo;
       const float u = ext > 0.f ? (c - lo) / ext : 0.f;
       const float sc = u * cells;
@@ -202,9 +203,11 @@ __global__ void k_keys(const float* __restrict__ v, uint32_t nv, const uint32_t*
 // the waits end.  Every wait is also bounded: a timeout sets a flag that the
 // host reports as an error.  (No global ticket counter: one atomic per
 // workgroup on a single word serialises at tens of ns each.)
-constexpr int kRsThreads = 256;
+constexpr int kRsThreads = 256;                         // histogram workgroups
+constexpr int kRsTile = 4096;                           // keys per histogram unit of work
+constexpr int kPassThreads = 512;              // pass workgroups
 constexpr int kRsRowsPerWave = 16;
-constexpr int kRsTile = kRsThreads * kRsRowsPerWave;  // 4096 keys per tile
+constexpr int kPassTile = kPassThreads * kRsRowsPerWave;  // keys per tile
 constexpr uint32_t kRsMaxPasses = 8;
 constexpr uint32_t kRsSpinLimit = 1u << 20;
 constexpr uint32_t kLookback = 16;   // look-back words read per round trip
@@ -215,28 +218,33 @@ struct SortCtl {                                // zeroed before the sort
 };
 constexpr size_t kSortCtlBytes = (sizeof(SortCtl) + 255) & ~size_t(255);
 
-// Look-back word of (tile, digit): high half = 2 (pass + 1) + inclusive, low
-// half = the tile's count of the digit (aggregate) or the count over tiles
-// 0..tile (inclusive).  A word with another pass in its tag is not yet written
-// for this pass.
-__device__ __forceinline__ uint64_t lb_word(uint32_t pass, bool incl, uint32_t v) {
-  return ((uint64_t)(2u * (pass + 1u) + (incl ? 1u : 0u)) << 32) | v;
-}
+// Look-back word of (pass, tile, digit), one array per pass, cleared before
+// the sort: 0 = not yet published; else bit 31 = inclusive and the low bits =
+// 1 + the tile's count of the digit (aggregate) or 1 + the count over tiles
+// 0..tile (inclusive; below n < 2^31, so it fits).
+__device__ __forceinline__ uint32_t lb_word(bool incl, uint32_t v) { return (incl ? 0x80000000u : 0u) | (v + 1u); }
 
-// Lanes of the wave (among those with ok set) holding the same digit d.
+// Lanes of the wave (among those with ok set) whose digit has the same low 8
+// bits as d: per bit, the ballot of lanes with the bit set, xor-ed with this
+// lane's bit spread over a word, marks the lanes that differ in it; the union
+// over the bits is the complement (four VALU instructions per bit).
 __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool ok) {
-  uint64_t same = __ballot(ok);
+  uint32_t diff_lo = 0u, diff_hi = 0u;
 #pragma unroll
   for (int bit = 0; bit < 8; ++bit) {
-    const uint64_t m = __ballot((d >> bit) & 1u);
-    same &= ((d >> bit) & 1u) ? m : ~m;
+    const uint32_t x = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, bit, 1);   // all ones if the bit is set
+    const uint64_t m = __ballot(x != 0u);
+    // diff | (m ^ x) in one instruction (truth table over (diff, m, x))
+    diff_lo = __builtin_amdgcn_bitop3_b32(diff_lo, (uint32_t)m, x, 0xF6);
+    diff_hi = __builtin_amdgcn_bitop3_b32(diff_hi, (uint32_t)(m >> 32), x, 0xF6);
   }
-  return same;
+  return ~(((uint64_t)diff_hi << 32) | diff_lo) & __ballot(ok);
 }
 
-// Exclusive scan of one value per thread across the 256-thread workgroup
-// (wave scans, then the four wave totals); *total = the workgroup's sum.
-// s4: 4 words of LDS.
+// Exclusive scan of one value per thread across a workgroup of T threads
+// (wave scans, then the wave totals); *total = the workgroup's sum.  s4: T / 64
+// words of LDS.
+template <int T>
 __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* s4, uint32_t* total) {
   const uint32_t lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   uint32_t x = v;
@@ -249,7 +257,7 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* s4, ui
   __syncthreads();
   uint32_t pre = 0, all = 0;
 #pragma unroll
-  for (uint32_t q = 0; q < kRsThreads / kWave; ++q) {
+  for (uint32_t q = 0; q < T / kWave; ++q) {
     const uint32_t t = s4[q];
     pre += q < w ? t : 0u;
     all += t;
@@ -261,20 +269,27 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* s4, ui
 
 // Digit counts of all passes: each wave takes 8 rows of 64 keys at a time
 // (their loads issued together) and adds each key's digit of each pass to the
-// workgroup's LDS histogram (LDS atomics; a row whose keys share the digit
-// adds once), which is then stored whole as the workgroup's row of `part`
-// (passes x 256 counts).  k_sort_hist_sum adds the rows up: a few thousand
-// global atomic adds to distinct words, instead of one per bin and workgroup.
+// workgroup's LDS histogram, which is then stored whole as the workgroup's row
+// of `part` (passes x 256 counts).  A row whose keys share the digit adds
+// once (the high digits of a spatially coherent input); otherwise every key
+// adds one to copy (lane mod C) of the histogram, so that lanes with equal
+// digits, which serialise on one LDS word, are spread over C words in
+// different banks (copies 257 words apart).  k_sort_hist_sum adds the rows
+// up: a few thousand global atomic adds to distinct words, instead of one per
+// bin and workgroup.
 constexpr uint32_t kHistRows = 8;
 constexpr uint32_t kHistMaxBlocks = 1024;
 constexpr uint32_t kHistSumRows = 32;    // partial rows per thread of the sum
+constexpr uint32_t kHistCopies = 4;
 __global__ __launch_bounds__(kRsThreads) void k_sort_hist(const uint64_t* __restrict__ keys, uint32_t n,
                                                            uint32_t lo_bit, uint32_t passes,
                                                            uint32_t* __restrict__ part) {
-  __shared__ uint32_t h[kRsMaxPasses][256];
-  for (uint32_t i = threadIdx.x; i < kRsMaxPasses * 256; i += kRsThreads) (&h[0][0])[i] = 0u;
+  extern __shared__ uint32_t h[];   // [passes][kHistCopies][257]
+  const uint32_t words = passes * kHistCopies * 257u;
+  for (uint32_t i = threadIdx.x; i < words; i += kRsThreads) h[i] = 0u;
   __syncthreads();
   const uint32_t lane = threadIdx.x % kWave;
+  const uint32_t copy = (lane % kHistCopies) * 257u;
   const uint64_t rows = ((uint64_t)n + kWave - 1) / kWave;
   const uint64_t waves = (uint64_t)gridDim.x * (kRsThreads / kWave);
   for (uint64_t r0 = ((uint64_t)blockIdx.x * (kRsThreads / kWave) + threadIdx.x / kWave) * kHistRows; r0 < rows;
@@ -292,20 +307,25 @@ __global__ __launch_bounds__(kRsThreads) void k_sort_hist(const uint64_t* __rest
       const uint64_t live = __ballot(ok);
       for (uint32_t p = 0; p < passes; ++p) {
         const uint32_t d = (uint32_t)(k[j] >> (lo_bit + 8u * p)) & 255u;
-        // a row whose live keys share one digit (common for the high digits
-        // of a spatially coherent input) costs one add
+        uint32_t* hp = h + p * (kHistCopies * 257u);
         const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
         if (__ballot(ok && d == d0) == live) {
-          if (lane == 0) atomicAdd(&h[p][d0], (uint32_t)__popcll(live));
+          if (lane == 0) atomicAdd(hp + d0, (uint32_t)__popcll(live));
         } else if (ok) {
-          atomicAdd(&h[p][d], 1u);
+          atomicAdd(hp + copy + d, 1u);
         }
       }
     }
   }
   __syncthreads();
   uint32_t* row = part + (uint64_t)blockIdx.x * passes * 256u;
-  for (uint32_t i = threadIdx.x; i < passes * 256u; i += kRsThreads) row[i] = (&h[0][0])[i];
+  for (uint32_t i = threadIdx.x; i < passes * 256u; i += kRsThreads) {
+    const uint32_t* hp = h + (i >> 8) * (kHistCopies * 257u) + (i & 255u);
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kHistCopies; ++q) c += hp[q * 257u];
+    row[i] = c;
+  }
 }
 
 // Workgroup (p, c): thread d adds digit d of pass p over partial rows
@@ -325,27 +345,30 @@ __global__ __launch_bounds__(kRsThreads) void k_sort_hist_sum(const uint32_t* __
 // of the tile (a row = 64 consecutive keys) in order: lanes holding the same
 // digit are found with eight ballots, their order inside the row comes from
 // the lane mask below them, and a per-wave running count per digit carries
-// the order across rows.  A per-digit prefix over the four waves and an
-// exclusive scan over the 256 digits give each key its place in the tile
-// sorted by digit; the tile is reordered in LDS, and thread t then writes
-// tile positions t, t + 256, ... to the digit's global start, plus the keys
-// with that digit in earlier tiles, plus the position inside the digit's run,
-// so consecutive threads store consecutive addresses of one run.
-__global__ __launch_bounds__(kRsThreads) void k_sort_pass(const uint64_t* __restrict__ kin,
-                                                           uint64_t* __restrict__ kout, uint32_t n, uint32_t shift,
-                                                           uint32_t pass, SortCtl* ctl, uint64_t* lb) {
-  __shared__ uint32_t wc[kRsThreads / kWave][257];
+// the order across rows.  A per-digit prefix over the waves and an exclusive
+// scan over the 256 digits give each key its place in the tile sorted by
+// digit; the tile is reordered in LDS, and thread t then writes tile
+// positions t, t + T, ... to the digit's global start, plus the keys with
+// that digit in earlier tiles, plus the position inside the digit's run, so
+// consecutive threads store consecutive addresses of one run.  Threads
+// 0..255 also stand for the 256 digits (publication and look-back).
+__global__ __launch_bounds__(kPassThreads) void k_sort_pass(const uint64_t* __restrict__ kin,
+                                                             uint64_t* __restrict__ kout, uint32_t n,
+                                                             uint32_t shift, uint32_t pass, SortCtl* ctl,
+                                                             uint32_t* lb) {
+  constexpr int kWaves = kPassThreads / kWave;
+  __shared__ uint32_t wc[kWaves][257];
   __shared__ uint32_t lstart[256];
   __shared__ uint32_t gbase[256];
-  __shared__ uint32_t scan_s[kRsThreads / kWave];
-  __shared__ uint64_t tk[kRsTile];
+  __shared__ uint32_t scan_s[kWaves];
+  __shared__ uint64_t tk[kPassTile];
   const uint32_t w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  for (uint32_t i = threadIdx.x; i < (kRsThreads / kWave) * 257; i += kRsThreads) (&wc[0][0])[i] = 0;
+  for (uint32_t i = threadIdx.x; i < kWaves * 257; i += kPassThreads) (&wc[0][0])[i] = 0;
   __syncthreads();
   const uint32_t tile = blockIdx.x;
   uint64_t key[kRsRowsPerWave];
   uint32_t dig[kRsRowsPerWave], rk[kRsRowsPerWave];
-  const uint64_t base = (uint64_t)tile * kRsTile + (uint64_t)w * kRsRowsPerWave * kWave;
+  const uint64_t base = (uint64_t)tile * kPassTile + (uint64_t)w * kRsRowsPerWave * kWave;
   const uint64_t lt = (1ull << lane) - 1ull;
 #pragma unroll
   for (int r = 0; r < kRsRowsPerWave; ++r) {
@@ -364,20 +387,25 @@ __global__ __launch_bounds__(kRsThreads) void k_sort_pass(const uint64_t* __rest
     if (ok && (same & lt) == 0ull) wc[w][d] = prev + (uint32_t)__popcll(same);
   }
   __syncthreads();
-  const uint32_t d = threadIdx.x;  // 256 threads, one per digit
+  const bool is_digit = threadIdx.x < 256u;
+  const uint32_t d = threadIdx.x & 255u;   // the digit of threads 0..255
   uint32_t run = 0;
+  if (is_digit) {
 #pragma unroll
-  for (int q = 0; q < kRsThreads / kWave; ++q) {
-    const uint32_t c = wc[q][d];
-    wc[q][d] = run;
-    run += c;
+    for (int q = 0; q < kWaves; ++q) {
+      const uint32_t c = wc[q][d];
+      wc[q][d] = run;
+      run += c;
+    }
   }
   // publish this tile's count of digit d (tile 0: already the inclusive count)
-  uint64_t* const my = lb + (uint64_t)tile * 256u + d;
-  __hip_atomic_store(my, lb_word(pass, tile == 0u, run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t* const lbp = lb + (uint64_t)pass * gridDim.x * 256u;
+  uint32_t* const my = lbp + (uint64_t)tile * 256u + d;
+  if (is_digit) __hip_atomic_store(my, lb_word(tile == 0u, run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   uint32_t total;
-  lstart[d] = block_exclusive(run, scan_s, &total);
-  const uint32_t gstart = block_exclusive(ctl->hist[pass][d], scan_s, &total);
+  const uint32_t ls = block_exclusive<kPassThreads>(is_digit ? run : 0u, scan_s, &total);
+  if (is_digit) lstart[d] = ls;
+  const uint32_t gstart = block_exclusive<kPassThreads>(is_digit ? ctl->hist[pass][d] : 0u, scan_s, &total);
 #pragma unroll
   for (int r = 0; r < kRsRowsPerWave; ++r) {
     if (dig[r] < 256u) tk[lstart[dig[r]] + wc[w][dig[r]] + rk[r]] = key[r];
@@ -386,44 +414,44 @@ __global__ __launch_bounds__(kRsThreads) void k_sort_pass(const uint64_t* __rest
   // round trip: add published counts from the nearest tile down, up to and
   // including the first inclusive one; an unpublished tile ends the window
   // and is read again.
-  uint32_t before = 0;
-  if (tile > 0u) {
-    uint32_t j = tile, spins = 0;   // tiles below j are still to be added
-    for (;;) {
-      uint64_t wd[kLookback];
+  if (is_digit) {
+    uint32_t before = 0;
+    if (tile > 0u) {
+      uint32_t j = tile, spins = 0;   // tiles below j are still to be added
+      for (;;) {
+        uint32_t wd[kLookback];
 #pragma unroll
-      for (uint32_t q = 0; q < kLookback; ++q)
-        wd[q] = q < j ? __hip_atomic_load(lb + (uint64_t)(j - 1u - q) * 256u + d, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT)
-                      : 0ull;
-      bool done = false;
-      uint32_t used = 0;
+        for (uint32_t q = 0; q < kLookback; ++q)
+          wd[q] = q < j ? __hip_atomic_load(lbp + (uint64_t)(j - 1u - q) * 256u + d, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                        : 0u;
+        bool done = false;
+        uint32_t used = 0;
 #pragma unroll
-      for (uint32_t q = 0; q < kLookback; ++q) {
-        if (done || used != q || q >= j) continue;
-        const uint32_t tag = (uint32_t)(wd[q] >> 32);
-        if ((tag >> 1) != pass + 1u) continue;    // not yet published: stop the window here
-        before += (uint32_t)wd[q];
-        used = q + 1u;
-        done = (tag & 1u) != 0u;
-      }
-      j -= used;
-      if (done || j == 0u) break;
-      if (used == 0u) {
-        if (++spins > kRsSpinLimit) {
-          __hip_atomic_store(&ctl->timeout, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
+        for (uint32_t q = 0; q < kLookback; ++q) {
+          if (done || used != q || q >= j || wd[q] == 0u) continue;   // a zero word ends the window
+          before += (wd[q] & 0x7fffffffu) - 1u;
+          used = q + 1u;
+          done = (wd[q] >> 31) != 0u;
         }
-        __builtin_amdgcn_s_sleep(1);
+        j -= used;
+        if (done || j == 0u) break;
+        if (used == 0u) {
+          if (++spins > kRsSpinLimit) {
+            __hip_atomic_store(&ctl->timeout, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
       }
+      __hip_atomic_store(my, lb_word(true, before + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __hip_atomic_store(my, lb_word(pass, true, before + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    gbase[d] = gstart + before - lstart[d];
   }
-  gbase[d] = gstart + before - lstart[d];
   __syncthreads();
-  const uint64_t tile0 = (uint64_t)tile * kRsTile;
-  const uint32_t valid = n - tile0 < (uint64_t)kRsTile ? (uint32_t)(n - tile0) : (uint32_t)kRsTile;
-  for (uint32_t i = threadIdx.x; i < valid; i += kRsThreads) {
+  const uint64_t tile0 = (uint64_t)tile * kPassTile;
+  const uint32_t valid = n - tile0 < (uint64_t)kPassTile ? (uint32_t)(n - tile0) : (uint32_t)kPassTile;
+  for (uint32_t i = threadIdx.x; i < valid; i += kPassThreads) {
     const uint64_t k = tk[i];
     const uint32_t pos = gbase[(uint32_t)(k >> shift) & 255u] + i;
     if (pos < n) kout[pos] = k;   // always, unless a look-back wait timed out
@@ -457,13 +485,14 @@ __global__ __launch_bounds__(kTreeThreads) void k_emit_tree(const float* __restr
     uint32_t o = (uint32_t)(sorted[sp] & index_mask);
     if (o >= nt) o = nt - 1u;   // only after a sort timeout, which rejects the mesh
     orig[sp] = o;
+    const u3u fi = gload3<u3u>(f, o);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const uint32_t vi = f[3ull * o + c];
+      const uint32_t vi = fi[c];
       if (fl) fl[3ull * sp + c] = vi;
-      const uint32_t vr = vi < nv ? vi : nv - 1u;
+      const f3u p = gload3<f3u>(v, vi < nv ? vi : nv - 1u);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) st[9 * i + 3 * c + k] = v[3ull * vr + k];
+      for (int k = 0; k < 3; ++k) st[9 * i + 3 * c + k] = p[k];
     }
   }
   __syncthreads();
@@ -573,15 +602,16 @@ hipError_t launch_keys(const float* v, uint32_t nv, const uint32_t* f, uint32_t 
 }
 
 static uint32_t hist_blocks(uint32_t n) {
-  const uint32_t tiles = (uint32_t)(((uint64_t)n + kRsTile - 1) / kRsTile);
-  return tiles < kHistMaxBlocks ? tiles : kHistMaxBlocks;
+  const uint32_t units = (uint32_t)(((uint64_t)n + kRsTile - 1) / kRsTile);
+  return units < kHistMaxBlocks ? units : kHistMaxBlocks;
 }
 
-// SortCtl, the look-back words (one per tile and digit), the histogram
+static uint64_t pass_tiles(uint32_t n) { return ((uint64_t)n + kPassTile - 1) / kPassTile; }
+
+// SortCtl, the look-back words (one per pass, tile and digit), the histogram
 // partials (one row of up to 8 x 256 counts per histogram workgroup)
 size_t sort_workspace_bytes(uint32_t n) {
-  const uint64_t tiles = ((uint64_t)n + kRsTile - 1) / kRsTile;
-  return kSortCtlBytes + (size_t)tiles * 256u * sizeof(uint64_t) +
+  return kSortCtlBytes + (size_t)kRsMaxPasses * pass_tiles(n) * 256u * sizeof(uint32_t) +
          (size_t)hist_blocks(n) * kRsMaxPasses * 256u * sizeof(uint32_t);
 }
 
@@ -591,19 +621,19 @@ hipError_t launch_sort(uint64_t* keys, uint64_t* keys_tmp, uint32_t n, uint32_t 
                        hipStream_t s, int* result_in_tmp) {
   const uint32_t passes = (nbits + 7u) / 8u;
   if (n == 0 || passes == 0 || passes > kRsMaxPasses || lo_bit + nbits > 64u) return hipErrorInvalidValue;
-  const uint32_t tiles = (uint32_t)(((uint64_t)n + kRsTile - 1) / kRsTile);
+  const uint32_t tiles = (uint32_t)pass_tiles(n);
   SortCtl* ctl = reinterpret_cast<SortCtl*>(ws);
-  uint64_t* lb = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(ws) + kSortCtlBytes);
-  uint32_t* part = reinterpret_cast<uint32_t*>(lb + (uint64_t)tiles * 256u);
+  uint32_t* lb = reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(ws) + kSortCtlBytes);
+  uint32_t* part = lb + (uint64_t)kRsMaxPasses * tiles * 256u;
   // the partial rows are written whole before they are read: clear the rest
-  hipError_t e = hipMemsetAsync(ws, 0, kSortCtlBytes + (size_t)tiles * 256u * sizeof(uint64_t), s);
+  hipError_t e = hipMemsetAsync(ws, 0, kSortCtlBytes + (size_t)passes * tiles * 256u * sizeof(uint32_t), s);
   if (e != hipSuccess) return e;
   const uint32_t hb = hist_blocks(n);
-  k_sort_hist<<<hb, kRsThreads, 0, s>>>(keys, n, lo_bit, passes, part);
+  k_sort_hist<<<hb, kRsThreads, passes * kHistCopies * 257u * sizeof(uint32_t), s>>>(keys, n, lo_bit, passes, part);
   k_sort_hist_sum<<<dim3(passes, (hb + kHistSumRows - 1) / kHistSumRows), kRsThreads, 0, s>>>(part, hb, passes, ctl);
   uint64_t *ki = keys, *ko = keys_tmp;
   for (uint32_t p = 0; p < passes; ++p) {
-    k_sort_pass<<<tiles, kRsThreads, 0, s>>>(ki, ko, n, lo_bit + 8u * p, p, ctl, lb);
+    k_sort_pass<<<tiles, kPassThreads, 0, s>>>(ki, ko, n, lo_bit + 8u * p, p, ctl, lb);
     uint64_t* t = ki;
     ki = ko;
     ko = t;

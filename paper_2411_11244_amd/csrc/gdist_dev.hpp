@@ -42,6 +42,12 @@ typedef float f2v __attribute__((ext_vector_type(2)));
 // 16-byte piece of a 24-byte box or a 36-byte triangle is one instruction.
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f3u __attribute__((ext_vector_type(3), aligned(4)));        // a vertex
+typedef uint32_t u3u __attribute__((ext_vector_type(3), aligned(4)));     // a triangle's vertex indices
+template <typename V, typename T>
+__device__ __forceinline__ V gload3(const T* p, uint64_t i) {   // element i of an array of 3-vectors
+  return *reinterpret_cast<const __attribute__((address_space(1))) V*>(gptr(p) + 3ull * i);
+}
 template <typename T>
 __device__ __forceinline__ T gload(const __attribute__((address_space(1))) float* p) {
   return *reinterpret_cast<const __attribute__((address_space(1))) T*>(p);
