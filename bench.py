@@ -220,8 +220,8 @@ def build_timing(mesh, reps: int = 3) -> dict:
         gdist.gdist_destroy(ctx)
     del keep
     return {"ms": round(float(np.median(ts[1:])), 3), "tris": int(mesh.n_tris),
-            "input": "device-resident arrays; synchronous call (vertex pass, key pass, 8-pass radix sort, emit, "
-                     "refit of the local tree, two small copies back)"}
+            "input": "device-resident arrays; synchronous call (vertex pass, key pass, one-sweep radix sort over "
+                     "the Morton bits, tree emitted with its boxes, three small copies back)"}
 
 
 # ---------------------------------------------------------------- legs
@@ -269,7 +269,12 @@ def leg_batched(copy_gbs) -> dict:
     from paper_2411_11244_amd import gdist
     gold = {r["pair"]: r for r in (load_golden("batched_all") or [])}
     ctx = gdist.gdist_create(0)
+    tuned = None
     try:
+        path = os.path.join(TUNING, "batched_mi355x.json")
+        if os.path.exists(path):
+            from paper_2411_11244_amd import tune
+            tuned = tune.apply(ctx, path).get("best")
         hs, descs, total = [], [], 0
         for p in range(256):
             ma, mb, pa, pb, _ = g.batched_pair(1, p)
@@ -298,7 +303,7 @@ def leg_batched(copy_gbs) -> dict:
     pairs = [(r["tri_a"], r["tri_b"]) == (gold[p]["tri_a"], gold[p]["tri_b"]) for p, r in enumerate(res) if p in gold]
     st = stats[-1]
     return {"workload": "batched: 256 mesh pairs (seed 1), 1K-500K triangles each, one gdist_query_batch call",
-            "tris_total": total, "ms_per_call": round(ms, 3), "queries_per_s": round(256 / (ms * 1e-3), 1),
+            "launch_options": tuned, "tris_total": total, "ms_per_call": round(ms, 3), "queries_per_s": round(256 / (ms * 1e-3), 1),
             "plain_p50_ms": pct(lat, 50), "plain_p99_ms": pct(lat, 99),
             "plain_queries_per_s": round(256 / (sum(lat) * 1e-3), 1),
             "batched_equals_plain": all(a["distance"] == b["distance"] and (a["tri_a"], a["tri_b"]) ==

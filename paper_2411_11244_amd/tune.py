@@ -10,6 +10,7 @@ result, only the amount of work per round, the number of rounds and the
 locality of the trees' boxes in the caches.
 
     python -m paper_2411_11244_amd.tune --out tune.json   (needs the GPU)
+    python -m paper_2411_11244_amd.tune --workload batched --out batched.json
 
 For the serving core it sweeps the server's slots ("max_slots") and rounds
 per step ("rounds_per_step") together with the context options above on the
@@ -130,7 +131,7 @@ def tune_server(ctx: int, handles: List[int], burst, paced, grid: Dict[str, Iter
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="rings", choices=["rings", "tiny", "serving"])
+    ap.add_argument("--workload", default="rings", choices=["rings", "tiny", "batched", "serving"])
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--out", default="")
     ap.add_argument("--reps", type=int, default=3)
@@ -155,18 +156,28 @@ def main():
                 json.dump(res, f, indent=1)
         gdist.gdist_destroy(ctx)
         return
-    if args.workload == "rings":
-        w = g.rings(frames=args.frames)
-        sel = np.linspace(0, 99, args.frames).astype(int)
-        queries = [g.Query(0, 0, g.identity_pose(), g.rings_pose_b(int(f)), 0) for f in sel]
-        w.queries = queries
-    else:
-        w = g.tiny(0)
     ctx = gdist.gdist_create(0)
-    hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in w.meshes]
-    descs = [gdist.make_desc(hs[q.a], hs[q.b], q.pose_a, q.pose_b, q.mode) for q in w.queries]
-    grid = {"expand_budget": [1 << 20, 1 << 22], "k_cap": [7, 8], "blocks_per_cu": [0],
-            "front_capacity": [1 << 27], "group_size": [24, 20, 16, 12]}
+    if args.workload == "batched":
+        # the 256 mesh pairs of the batched workload (seed 1) in one call
+        descs = []
+        for p in range(256):
+            ma, mb, pa, pb, _ = g.batched_pair(1, p)
+            ha, hb = gdist.gdist_build(ctx, ma.verts, ma.tris), gdist.gdist_build(ctx, mb.verts, mb.tris)
+            descs.append(gdist.make_desc(ha, hb, pa, pb, 0))
+        grid = {"expand_budget": [1 << 18, 1 << 20, 1 << 22], "k_cap": [4, 6, 8], "blocks_per_cu": [0],
+                "front_capacity": [1 << 26], "group_size": [0]}
+    else:
+        if args.workload == "rings":
+            w = g.rings(frames=args.frames)
+            sel = np.linspace(0, 99, args.frames).astype(int)
+            queries = [g.Query(0, 0, g.identity_pose(), g.rings_pose_b(int(f)), 0) for f in sel]
+            w.queries = queries
+        else:
+            w = g.tiny(0)
+        hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in w.meshes]
+        descs = [gdist.make_desc(hs[q.a], hs[q.b], q.pose_a, q.pose_b, q.mode) for q in w.queries]
+        grid = {"expand_budget": [1 << 20, 1 << 22], "k_cap": [7, 8], "blocks_per_cu": [0],
+                "front_capacity": [1 << 27], "group_size": [24, 20, 16, 12]}
     t = time.time()
     res = tune(ctx, descs, grid, args.reps)
     res["workload"] = args.workload
