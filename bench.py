@@ -70,6 +70,10 @@ def parse():
     ap.add_argument("--plain-rate", type=float, default=2000.0,
                     help="offered queries/s at which the plain and served forms run the same arrivals")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the measured copy kernel")
+    ap.add_argument("--stats-in-timed-steps", type=int, default=0,
+                    help="1: the timed steps also count the work statistics")
+    ap.add_argument("--count-steps", type=int, default=1,
+                    help="steps run after the timed ones with the work statistics on (byte counts)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the timed steps, run one elementwise copy reading and writing this many MiB "
                          "(the scale for rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -110,12 +114,17 @@ def copy_peak_gbs(mib: int) -> dict:
     return {"gbs": round(2 * (mib << 20) / (ms * 1e-3) / 1e9, 1), "mib": mib, "ms": round(ms, 4)}
 
 
-def trav_roofline(stats, copy_gbs=None) -> dict:
-    """k_traverse roofline from the kernel's own counters and HIP events."""
+def trav_roofline(stats, copy_gbs=None, counted=None) -> dict:
+    """k_traverse roofline from the kernel's own counters and HIP events.
+    `stats`: the timed calls (launch times); `counted`: calls of the same work
+    run with the statistics on, whose byte counts give the bytes per launch
+    (default: the timed calls themselves)."""
     ms = sum(s["ms_traverse_kernel"] for s in stats)
     launches = sum(s["traverse_launches"] for s in stats)
-    b_trav = sum(s["bytes_traversal"] for s in stats)
-    b_narrow = sum(s["bytes_narrow"] for s in stats)
+    cnt = counted if counted else stats
+    c_launches = max(1, sum(s["traverse_launches"] for s in cnt))
+    b_trav = sum(s["bytes_traversal"] for s in cnt) / c_launches * launches
+    b_narrow = sum(s["bytes_narrow"] for s in cnt) / c_launches * launches
     avg = ms / max(1, launches)
     gbs = (b_trav + b_narrow) / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     out = {"bound": "hbm", "kernel": "k_traverse", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -230,6 +239,7 @@ def leg_tiny(copy_gbs) -> dict:
     import oracle
     from paper_2411_11244_amd import gdist
     ctx = gdist.gdist_create(0)
+    gdist.gdist_set_option(ctx, "stats", 0)
     rows = []
     try:
         for seed in range(10):
@@ -281,6 +291,7 @@ def leg_batched(copy_gbs) -> dict:
             ha, hb = gdist.gdist_build(ctx, ma.verts, ma.tris), gdist.gdist_build(ctx, mb.verts, mb.tris)
             total += ma.n_tris + mb.n_tris
             descs.append(gdist.make_desc(ha, hb, pa, pb, 0))
+        gdist.gdist_set_option(ctx, "stats", 0)
         for _ in range(2):
             gdist.gdist_query_batch(ctx, descs)
         ts, stats = [], []
@@ -296,12 +307,16 @@ def leg_batched(copy_gbs) -> dict:
                                   (np.array(d.pb.R).reshape(3, 3), np.array(d.pb.t)), 0)
             lat.append((time.perf_counter() - t) * 1e3)
             plain.append(r)
+        # one more call with the work statistics on: the byte and work counts
+        gdist.gdist_set_option(ctx, "stats", 1)
+        gdist.gdist_query_batch(ctx, descs)
+        counted = [gdist.gdist_last_stats(ctx)]
     finally:
         gdist.gdist_destroy(ctx)
     ms = float(np.median(ts)) * 1e3
     errs = [abs(r["distance"] - gold[p]["distance"]) for p, r in enumerate(res) if p in gold]
     pairs = [(r["tri_a"], r["tri_b"]) == (gold[p]["tri_a"], gold[p]["tri_b"]) for p, r in enumerate(res) if p in gold]
-    st = stats[-1]
+    st = counted[-1]
     return {"workload": "batched: 256 mesh pairs (seed 1), 1K-500K triangles each, one gdist_query_batch call",
             "launch_options": tuned, "tris_total": total, "ms_per_call": round(ms, 3), "queries_per_s": round(256 / (ms * 1e-3), 1),
             "plain_p50_ms": pct(lat, 50), "plain_p99_ms": pct(lat, 99),
@@ -310,7 +325,7 @@ def leg_batched(copy_gbs) -> dict:
                                         (b["tri_a"], b["tri_b"]) for a, b in zip(res, plain)),
             "oracle_checked": len(errs), "max_abs_err_vs_oracle": max(errs) if errs else None,
             "pairs_equal_oracle": all(pairs) if pairs else None,
-            "roofline": trav_roofline(stats, copy_gbs),
+            "roofline": trav_roofline(stats, copy_gbs, counted),
             "counts": {k: st[k] for k in ("rounds", "entries_popped", "child_pairs", "child_boxes", "entries_pushed",
                                           "leaf_pairs", "leaf_tris", "tri_pairs", "tri_full", "candidates")}}
 
@@ -327,6 +342,7 @@ def leg_hard(copy_gbs) -> dict:
         ha, hb = gdist.gdist_build(ctx, A.verts, A.tris), gdist.gdist_build(ctx, B.verts, B.tris)
         for mode, name, reps in ((0, "min", 5), (1, "max", 3)):
             q = w.queries[mode]
+            gdist.gdist_set_option(ctx, "stats", 0)
             gdist.gdist_query(ctx, ha, hb, q.pose_a, q.pose_b, mode)
             ts, stats = [], []
             for _ in range(reps):
@@ -334,6 +350,9 @@ def leg_hard(copy_gbs) -> dict:
                 r = gdist.gdist_query(ctx, ha, hb, q.pose_a, q.pose_b, mode)
                 ts.append((time.perf_counter() - t) * 1e3)
                 stats.append(gdist.gdist_last_stats(ctx))
+            gdist.gdist_set_option(ctx, "stats", 1)   # one counted call: the byte and work counts
+            gdist.gdist_query(ctx, ha, hb, q.pose_a, q.pose_b, mode)
+            counted = [gdist.gdist_last_stats(ctx)]
             gold = (load_golden("hard_max" if mode else "hard_min") or [None])[0]
             st = stats[-1]
             out[name] = {"ms_median": pct(ts, 50), "device_ms": round(st["ms_total"], 3), "rounds": st["rounds"],
@@ -342,7 +361,7 @@ def leg_hard(copy_gbs) -> dict:
                          "abs_err_vs_oracle": abs(r["distance"] - gold["distance"]) if gold else None,
                          "pair_equals_oracle": ((r["tri_a"], r["tri_b"]) == (gold["tri_a"], gold["tri_b"]))
                                                if gold else None,
-                         "n_ties": r["n_ties"], "roofline": trav_roofline(stats, copy_gbs)}
+                         "n_ties": r["n_ties"], "roofline": trav_roofline(stats, copy_gbs, counted)}
     finally:
         gdist.gdist_destroy(ctx)
     return out
@@ -364,6 +383,7 @@ def leg_serving(n_queries: int, rates, plain_rate: float) -> dict:
     rows = []
     try:
         tune.apply(ctx, path)
+        gdist.gdist_set_option(ctx, "stats", 0)
         sc = tune.server_config(path)
         hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in pool]
         cmp = compare(ctx, hs, qs, None, keep_plain=True)
@@ -422,6 +442,10 @@ def main():
     h = gdist.gdist_build(ctx, mesh.verts, mesh.tris)
     info = gdist.gdist_mesh_info(ctx, h)
     descs = [gdist.make_desc(h, h, q.pose_a, q.pose_b, gdist.GDIST_MIN) for q in w.queries]
+    # timed steps without the work statistics (diagnostic counters, not part
+    # of the method); the same step is then run --count-steps times with them
+    # on for the byte and work counts
+    gdist.gdist_set_option(ctx, "stats", 1 if args.stats_in_timed_steps else 0)
 
     # ---- warmup + timed steps: one batched call over all frames per step
     for _ in range(args.warmup):
@@ -436,6 +460,13 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     qps = args.frames * args.steps / (t1 - t0)
+    counted = []
+    if args.count_steps > 0:
+        gdist.gdist_set_option(ctx, "stats", 1)
+        for _ in range(args.count_steps):
+            gdist.gdist_query_batch(ctx, descs)
+            counted.append(gdist.gdist_last_stats(ctx))
+        gdist.gdist_set_option(ctx, "stats", 1 if args.stats_in_timed_steps else 0)
     if args.calibrate_copy_mib > 0:
         n = args.calibrate_copy_mib << 18
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -448,7 +479,7 @@ def main():
 
     # ---- dominant kernel: k_traverse, timed by the library's HIP events
     # around each of its launches on the library's stream (the timed steps only)
-    roof = trav_roofline(stats, copy_gbs)
+    roof = trav_roofline(stats, copy_gbs, counted)
     pmc = traffic_record()
     avg_s = roof["avg_ms_per_launch"] * 1e-3
     roof["traffic"] = pmc["traffic_bytes_per_launch"] if pmc else None
@@ -529,7 +560,8 @@ def main():
         "copy_kernel": copy,
         "refit": refit,
         "build": build,
-        "stats_last_step": stats[-1],
+        "stats_in_timed_steps": bool(args.stats_in_timed_steps),
+        "stats_last_step": counted[-1] if counted else stats[-1],
         "batched_equals_plain": agree,
         "cpu_baseline": cpu,
         "verify": verify,

@@ -174,6 +174,11 @@ gdist_status_t gdist_destroy(gdist_ctx_t ctx);
  *                     change.  0 (default) forgets the pairs.  gdist_query and
  *                     the batch calls use it; a server does not record pairs
  *   "memory_budget"   device bytes the context may hold (0 = unlimited)
+ *   "stats"           1 (default) = traversals count the work statistics that
+ *                     gdist_last_stats reports (entries, child pairs, leaf and
+ *                     triangle pairs, bytes); 0 = they do not (a few per cent
+ *                     faster; those fields then read 0, rounds and the front
+ *                     peak are still counted).  Results do not change.
  */
 gdist_status_t gdist_set_option(gdist_ctx_t ctx, const char* key, double value);
 

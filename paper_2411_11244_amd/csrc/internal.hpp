@@ -135,6 +135,7 @@ struct TravParams {
                            //    with larger regions); 0: it only marks the slot
   const uint32_t* finish;  // re-evaluation over slots 0 .. n_list-1 where finish[slot] == 1
                            //   (nullptr: every listed slot)
+  uint32_t stats;          // 1: count the work statistics (ST_*; rounds and the peak always)
 };
 
 // Head of the report of one serving step (device buffer, copied to pinned

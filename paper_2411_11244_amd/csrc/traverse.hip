@@ -149,17 +149,30 @@ __device__ __forceinline__ void append(bool take, const E& e, E* buf, uint32_t* 
 }
 
 // Per-wave counters (wave-uniform values), flushed to LDS once per kernel.
+// The launch without statistics instantiates ON = false, where counting
+// compiles to nothing.
+template <bool ON>
 struct WaveStats {
   uint32_t v[ST_N];
 };
-__device__ __forceinline__ void add_stat(WaveStats& ws, int idx, bool pred) {
-  ws.v[idx] += (uint32_t)__popcll(__ballot(pred));
+template <bool ON>
+__device__ __forceinline__ void add_stat(WaveStats<ON>& ws, int idx, bool pred) {
+  if constexpr (ON) ws.v[idx] += (uint32_t)__popcll(__ballot(pred));
 }
 // Per-lane byte-count operands (summed over the wave once per round): child
 // boxes read per popped entry and triangles read per leaf pair.
+template <bool ON>
 struct LaneStats {
   uint32_t boxes, ltris;
 };
+template <bool ON>
+__device__ __forceinline__ void add_boxes(LaneStats<ON>& ls, uint32_t v) {
+  if constexpr (ON) ls.boxes += v;
+}
+template <bool ON>
+__device__ __forceinline__ void add_ltris(LaneStats<ON>& ls, uint32_t v) {
+  if constexpr (ON) ls.ltris += v;
+}
 
 __device__ __forceinline__ uint32_t level_of(uint32_t node) { return 31u - (uint32_t)__clz(node); }
 
@@ -616,10 +629,10 @@ __device__ __forceinline__ void append_runs4(const bool* take, const uint4* e, u
 // entry t >> 2k).  All entry loads of the R rows are issued before any result
 // is needed, and the survivors of the R rows are appended together.  Row
 // starts and bounds are wave-uniform.
-template <int R>
+template <int R, bool ON>
 __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base0,
-                                            uint32_t n_items, uint32_t kk, uint32_t lane, uint64_t lt, WaveStats& ws,
-                                            LaneStats& ls) {
+                                            uint32_t n_items, uint32_t kk, uint32_t lane, uint64_t lt,
+                                            WaveStats<ON>& ws, LaneStats<ON>& ls) {
   Ctl* c = p.ctl;
   uint4 ent[R];
   bool act[R];
@@ -659,7 +672,7 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
     a = a && (sub >> (kA + kB)) == 0u;
     add_stat(ws, ST_POPPED, a && sub == 0u);
     add_stat(ws, ST_CHILD, a);
-    ls.boxes += (a && sub == 0u) ? (1u << kA) + (1u << kB) : 0u;
+    add_boxes(ls, (a && sub == 0u) ? (1u << kA) + (1u << kB) : 0u);
     const uint32_t ca = (ent[r].x << kA) | (sub & ((1u << kA) - 1u));
     const uint32_t cb = (ent[r].y << kB) | (sub >> kA);
     bool keep = false;
@@ -667,14 +680,15 @@ __device__ __forceinline__ void expand_rows(const TravParams& p, BlockState* bs,
     if (a) {
       const Box ba = load_box(v.boxA, ca), bb = load_box(v.boxB, cb);
       const bool enh = v.enh != 0;
+      // (a culled pair's improving bound cannot help: not computed)
       if (mode == 0) {
         nkey = min_lower(ba, bb);
         keep = nkey - delta <= best;
-        improve = min_upper(ba, bb, enh) + delta;
+        improve = keep ? min_upper(ba, bb, enh) + delta : __builtin_huge_valf();
       } else {
         nkey = max_upper(ba, bb);
         keep = nkey + delta >= best;
-        improve = fmaxf(max_lower(ba, bb, enh) - delta, 0.f);
+        improve = keep ? fmaxf(max_lower(ba, bb, enh) - delta, 0.f) : 0.f;
       }
     }
     const bool isleaf = (ca >= v.LA) && (cb >= v.LB);
@@ -702,14 +716,16 @@ __device__ __forceinline__ void eval_child(const SlotView& v, bool valid, const 
   float nkey = 0.f;
   if (valid) {
     const bool enh = v.enh != 0;
+    // the improving bound of a culled pair cannot beat the running bound
+    // (it is at least as far from it as the culling bound): not computed
     if (v.mode == 0) {
       nkey = min_lower(ba, bb);
       keep = nkey - v.delta <= v.best;
-      imp = fminf(imp, min_upper(ba, bb, enh) + v.delta);
+      if (keep) imp = fminf(imp, min_upper(ba, bb, enh) + v.delta);
     } else {
       nkey = max_upper(ba, bb);
       keep = nkey + v.delta >= v.best;
-      imp = fmaxf(imp, fmaxf(max_lower(ba, bb, enh) - v.delta, 0.f));
+      if (keep) imp = fmaxf(imp, fmaxf(max_lower(ba, bb, enh) - v.delta, 0.f));
     }
   }
   const bool isleaf = (ca >= v.LA) && (cb >= v.LB);
@@ -734,10 +750,10 @@ __device__ __forceinline__ void eval_child(const SlotView& v, bool valid, const 
 // swap places in commutative sums, minima and maxima), so every child pair is
 // evaluated as (G box, S box) whichever side G is, with no branch on the
 // split: lanes of one wave may split differently.
-template <int R>
+template <int R, bool ON>
 __device__ __forceinline__ void expand_entries(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base0,
-                                               uint32_t n_ent, uint32_t lane, uint64_t lt, WaveStats& ws,
-                                               LaneStats& ls) {
+                                               uint32_t n_ent, uint32_t lane, uint64_t lt, WaveStats<ON>& ws,
+                                               LaneStats<ON>& ls) {
   Ctl* c = p.ctl;
   uint4 ent[R];
   bool act[R];
@@ -782,7 +798,7 @@ __device__ __forceinline__ void expand_entries(const TravParams& p, BlockState* 
     }
     if (a && quad) load_box_pair(gbox, gfirst + 2u, G + 2);
     add_stat(ws, ST_POPPED, a);
-    ls.boxes += a ? (1u << kA) + (1u << kB) : 0u;
+    add_boxes(ls, a ? (1u << kA) + (1u << kB) : 0u);
     // S's own node when it stays at its level
     if (kS == 0u && (sn & 1u)) S2[0] = S2[1];
     bool tl[4], tf[4];
@@ -883,9 +899,10 @@ __device__ __forceinline__ uint4 leaf_row(const BlockState* bs, const Round& rd,
   return ent;
 }
 
+template <bool ON>
 __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base,
                                                    uint32_t n_items, uint4 ent, uint32_t lane, uint64_t lt, uint4* q,
-                                                   uint32_t& qn, WaveStats& ws, LaneStats& ls) {
+                                                   uint32_t& qn, WaveStats<ON>& ws, LaneStats<ON>& ls) {
   bool act = base + lane < n_items;
   const uint32_t slot = ent.w;
   const SlotView v = slot_view(p, bs, rd.lds_slots, act, slot);
@@ -898,7 +915,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
   if (act) {
     leaf_range(ent.x, v.depthA, v.nA, sa, ea);
     leaf_range(ent.y, v.depthB, v.nB, sb, eb);
-    ls.ltris += (ea - sa) + (eb - sb);
+    add_ltris(ls, (ea - sa) + (eb - sb));
   }
   V3<float> P[2][3], Q[2][3];
   if (act) {
@@ -977,8 +994,9 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
 
 // Narrow phase, stage 2: exact FP32 triangle-triangle distance on queued pairs
 // (the filter queues min-mode pairs only).
+template <bool ON>
 __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs, bool lds, uint4 e, bool act,
-                                            uint32_t lane, uint64_t lt, WaveStats& ws) {
+                                            uint32_t lane, uint64_t lt, WaveStats<ON>& ws) {
   const uint32_t slot = e.x, pa = e.y, pb = e.z;
   const SlotView v = slot_view(p, bs, lds, act, slot);
   const uint32_t mode = v.mode;
@@ -1031,7 +1049,7 @@ __device__ __forceinline__ void world_tri(const float* tris, uint32_t pos, const
 // LDS_SLOTS: the per-query running bound and window live in LDS (n_slots <=
 // kLdsSlots); a compile-time choice, so no load has to pick between LDS and
 // global memory at run time.
-template <bool LDS_SLOTS>
+template <bool LDS_SLOTS, bool STATS>
 __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   __shared__ BlockState bs_;
   __shared__ uint4 sq[kTravWaves][kQueue];
@@ -1045,10 +1063,10 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   const uint32_t nw = gridDim.x * kTravWaves;
   uint4* q = sq[wib];
   constexpr bool lds_slots = LDS_SLOTS;
-  WaveStats ws;
+  WaveStats<STATS> ws;
 #pragma unroll
   for (int i = 0; i < ST_N; ++i) ws.v[i] = 0u;
-  LaneStats ls;
+  LaneStats<STATS> ls;
   ls.boxes = 0u;
   ls.ltris = 0u;
   if (tid < ST_N) bs->stats[tid] = 0ull;
@@ -1148,7 +1166,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
       }
       if (!more) break;
     }
-    {
+    if constexpr (STATS) {
       // the round's byte-count operands, summed per wave (kept per round so
       // the per-lane 32-bit sums cannot wrap)
       const uint32_t sb = wave_sum(ls.boxes), stt = wave_sum(ls.ltris);
@@ -1178,7 +1196,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     c->trace_end = (unsigned long long)wall_clock64();
     c->rounds_done = (uint32_t)bs->stats[ST_ROUNDS];
   }
-  if (lane == 0)
+  if (STATS && lane == 0)
     for (int i = 0; i < ST_N; ++i)
       if (i != ST_ROUNDS && i != ST_PEAK && i != ST_BOXES && i != ST_LTRI && ws.v[i])
         atomicAdd(&bs->stats[i], (unsigned long long)ws.v[i]);
@@ -1419,14 +1437,25 @@ hipError_t launch_slot_hist(const TravParams& p, uint32_t* live, hipStream_t s) 
   return hipGetLastError();
 }
 
+static const void* traverse_fn(const TravParams& p) {
+  const bool lds = p.n_slots <= kLdsSlots;
+  if (p.stats) return lds ? (const void*)k_traverse<true, true> : (const void*)k_traverse<false, true>;
+  return lds ? (const void*)k_traverse<true, false> : (const void*)k_traverse<false, false>;
+}
+
 hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, uint32_t* threads) {
-  int per_cu = 0;
-  int per_cu2 = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_traverse<true>, kTravBlock, 0);
-  if (e != hipSuccess) return e;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k_traverse<false>, kTravBlock, 0);
-  if (e != hipSuccess) return e;
-  if (per_cu2 < per_cu) per_cu = per_cu2;
+  // the smallest occupancy of the four instantiations (slot table in LDS or
+  // not, statistics or not): one grid size fits every launch
+  const void* fns[4] = {(const void*)k_traverse<true, true>, (const void*)k_traverse<false, true>,
+                        (const void*)k_traverse<true, false>, (const void*)k_traverse<false, false>};
+  int per_cu = 1 << 20;
+  hipError_t e = hipSuccess;
+  for (const void* fn : fns) {
+    int n = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kTravBlock, 0);
+    if (e != hipSuccess) return e;
+    if (n < per_cu) per_cu = n;
+  }
   hipDeviceProp_t prop;
   e = hipGetDeviceProperties(&prop, device);
   if (e != hipSuccess) return e;
@@ -1450,8 +1479,7 @@ hipError_t traverse_grid(int device, uint32_t blocks_per_cu, uint32_t* blocks, u
 hipError_t launch_traverse(const TravParams& p, uint32_t blocks, uint32_t threads, hipStream_t s) {
   TravParams pp = p;
   void* args[] = {&pp};
-  const void* fn = p.n_slots <= kLdsSlots ? (const void*)k_traverse<true> : (const void*)k_traverse<false>;
-  return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(threads), args, 0, s);
+  return hipLaunchCooperativeKernel(traverse_fn(p), dim3(blocks), dim3(threads), args, 0, s);
 }
 
 // Graph node of a traversal launch, marked cooperative like launch_traverse.
@@ -1461,7 +1489,7 @@ hipError_t add_traverse_node(hipGraph_t g, const TravParams& p, uint32_t blocks,
   void* args[] = {&pp};
   hipKernelNodeParams kp;
   std::memset(&kp, 0, sizeof(kp));
-  kp.func = p.n_slots <= kLdsSlots ? (void*)k_traverse<true> : (void*)k_traverse<false>;
+  kp.func = const_cast<void*>(traverse_fn(p));
   kp.gridDim = dim3(blocks);
   kp.blockDim = dim3(threads);
   kp.kernelParams = args;

@@ -492,3 +492,44 @@ def test_one_to_many_shared_refit(orc, gctx):
         gdist.gdist_release(gctx, ha)
         for h in hbs:
             gdist.gdist_release(gctx, h)
+
+
+def test_stats_off_same_results(orc):
+    """With the "stats" option off the traversal counts no work statistics
+    (those fields read 0; rounds still counted) and every result is the one
+    the counting traversal gives."""
+    rng = np.random.default_rng(31)
+    meshes = [g.random_mesh_of_size(rng, t) for t in (500, 3000, 9000, 40)]
+    descs = []
+    for i in range(10):
+        a, b = (int(x) for x in rng.integers(0, len(meshes), size=2))
+        gap = [-0.05, 2e-3, 0.1, 0.7][i % 4]
+        pa, pb = g.place_with_gap(rng, meshes[a], meshes[b], gap, g.random_rotation(rng), g.random_rotation(rng))
+        descs.append((a, b, pa, pb, i % 2))
+    out = {}
+    for on in (1, 0):
+        ctx = gdist.gdist_create(0)
+        try:
+            gdist.gdist_set_option(ctx, "stats", on)
+            hs = [build(ctx, m) for m in meshes]
+            res = gdist.gdist_query_batch(ctx, [gdist.make_desc(hs[a], hs[b], pa, pb, m) for a, b, pa, pb, m in descs])
+            single = gdist.gdist_query(ctx, hs[1], hs[2], descs[1][2], descs[1][3], 0)
+            st = gdist.gdist_last_stats(ctx)
+            out[on] = (res, single, st)
+        finally:
+            gdist.gdist_destroy(ctx)
+    (r1, s1, st1), (r0, s0, st0) = out[1], out[0]
+    for x, y in zip(r1 + [s1], r0 + [s0]):
+        assert x["distance"] == y["distance"]
+        assert (x["tri_a"], x["tri_b"], x["n_ties"]) == (y["tri_a"], y["tri_b"], y["n_ties"])
+    assert st1["child_pairs"] > 0 and st1["child_boxes"] > 0 and st1["leaf_tris"] > 0
+    assert st0["child_pairs"] == 0 and st0["child_boxes"] == 0 and st0["leaf_tris"] == 0
+    assert st0["rounds"] > 0
+    a, b, pa, pb, m = descs[0]
+    check_against_oracle(orc, r0[0], oracle_query(orc, meshes[a], pa, meshes[b], pb, m), meshes[a], pa, meshes[b], pb, m)
+    ctx = gdist.gdist_create(0)
+    try:
+        with pytest.raises(gdist.GdistError):
+            gdist.gdist_set_option(ctx, "stats", 2)
+    finally:
+        gdist.gdist_destroy(ctx)
