@@ -112,6 +112,7 @@ def main(argv=None) -> int:
     qs = g.serving_stream(pool, a.rate, a.queries, seed=a.seed + 1)
     ctx = gdist.gdist_create(0)
     try:
+        gdist.gdist_set_option(ctx, "stats", 0)   # diagnostic counters off while serving
         tuned = {}
         if a.tuning:
             from . import tune

@@ -143,6 +143,7 @@ def main():
         burst = g.serving_stream(pool, 50000.0, 2000, seed=7)
         paced = g.serving_stream(pool, 1000.0, 1000, seed=8)
         ctx = gdist.gdist_create(0)
+        gdist.gdist_set_option(ctx, "stats", 0)   # timed as served: diagnostic counters off
         hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in pool]
         grid = {"max_slots": [64, 128, 256], "rounds_per_step": [4, 8], "expand_budget": [1 << 18, 1 << 22],
                 "k_cap": [5, 8]}
@@ -157,6 +158,7 @@ def main():
         gdist.gdist_destroy(ctx)
         return
     ctx = gdist.gdist_create(0)
+    gdist.gdist_set_option(ctx, "stats", 0)   # timed as the bench times: diagnostic counters off
     if args.workload == "batched":
         # the 256 mesh pairs of the batched workload (seed 1) in one call
         descs = []
