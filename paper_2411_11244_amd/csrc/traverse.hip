@@ -103,29 +103,47 @@ __device__ void grid_sync(Ctl* c, uint32_t spin_limit) {
 __device__ __forceinline__ uint32_t first_lane(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
 
 // Improve the running bound of a slot: min mode lowers it, max mode raises it.
-// A wave whose active lanes share one slot reduces first and issues one atomic.
+// The active lanes are grouped by slot, up to four groups (the slots of the
+// lowest remaining lanes): each group reduces over the wave and its first lane
+// issues one atomic, only if that improves the bound; lanes of further slots
+// issue one each.  (Waves of batched calls mix slots; one atomic per lane on
+// the word of a busy slot serialises.)  lds_copy, if set, is this workgroup's
+// LDS copy of the bounds, updated the same way.
 __device__ __forceinline__ void improve_bound(uint32_t* target_base, size_t stride_words, bool act, uint32_t slot,
-                                              uint32_t mode, float v, uint32_t lane) {
+                                              uint32_t mode, float v, uint32_t lane, uint32_t* lds_copy = nullptr) {
   uint64_t am = __ballot(act);
   if (am == 0) return;
-  uint32_t fl = first_lane(am);
-  uint32_t s0 = lane_value(slot, fl);
-  uint32_t m0 = lane_value(mode, fl);
-  if (__ballot(act && slot != s0) == 0ull) {
-    float r = act ? v : (m0 == 0 ? __builtin_huge_valf() : 0.f);
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    if (am == 0ull) break;
+    const uint32_t fl = first_lane(am);
+    const uint32_t s0 = lane_value(slot, fl);
+    const uint32_t m0 = lane_value(mode, fl);
+    const uint64_t grp = __ballot(act && slot == s0) & am;
+    const bool in = (grp >> lane) & 1ull;
+    float r = in ? v : (m0 == 0 ? __builtin_huge_valf() : 0.f);
     r = m0 == 0 ? wave_min(r) : wave_max(r);
     if (lane == fl) {
       uint32_t* t = target_base + stride_words * s0;
       if (m0 == 0) {
         if (fbits(r) < ld_rlx(t)) atomicMin(t, fbits(r));
+        if (lds_copy) atomicMin(&lds_copy[s0], fbits(r));
       } else {
         if (fbits(r) > ld_rlx(t)) atomicMax(t, fbits(r));
+        if (lds_copy) atomicMax(&lds_copy[s0], fbits(r));
       }
     }
-  } else if (act) {
+    am &= ~grp;
+  }
+  if ((am >> lane) & 1ull) {
     uint32_t* t = target_base + stride_words * slot;
-    if (mode == 0) atomicMin(t, fbits(v));
-    else atomicMax(t, fbits(v));
+    if (mode == 0) {
+      atomicMin(t, fbits(v));
+      if (lds_copy) atomicMin(&lds_copy[slot], fbits(v));
+    } else {
+      atomicMax(t, fbits(v));
+      if (lds_copy) atomicMax(&lds_copy[slot], fbits(v));
+    }
   }
 }
 
@@ -458,12 +476,7 @@ __device__ __forceinline__ float get_delta(const TravParams& p, const BlockState
 // Improve a slot's running bound in memory and in this workgroup's LDS copy.
 __device__ __forceinline__ void improve_best(const TravParams& p, BlockState* bs, bool lds, bool act,
                                              uint32_t slot, uint32_t mode, float v, uint32_t lane) {
-  if (!__ballot(act)) return;
-  improve_bound(&p.st[0].best, sizeof(SlotState) / 4, act, slot, mode, v, lane);
-  if (lds && act) {
-    if (mode == 0) atomicMin(&bs->best[slot], fbits(v));
-    else atomicMax(&bs->best[slot], fbits(v));
-  }
+  improve_bound(&p.st[0].best, sizeof(SlotState) / 4, act, slot, mode, v, lane, lds ? bs->best : nullptr);
 }
 
 __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -858,23 +871,27 @@ __device__ __forceinline__ void put_candidate(const TravParams& p, uint32_t slot
   }
 }
 // Append the flagged lanes' candidates (d32 within the window of their slot's
-// bound) to their slots' regions.  When all of them belong to one slot (the
-// usual case) the wave takes their places with one atomic, else each lane
-// with its own.  Needs the whole wave.
+// bound) to their slots' regions.  The flagged lanes are grouped by slot, up
+// to four groups (the slots of the lowest remaining lanes), each taking its
+// places with one atomic; lanes of further slots take one each.  Needs the
+// whole wave.
 __device__ __forceinline__ void add_candidates(const TravParams& p, bool cand, uint32_t slot, uint32_t pa,
                                                uint32_t pb, float dd, uint32_t lane, uint64_t lt) {
-  const uint64_t m = __ballot(cand);
+  uint64_t m = __ballot(cand);
   if (m == 0ull) return;
-  const uint32_t fl = first_lane(m);
-  const uint32_t s0 = lane_value(slot, fl);
-  if (__ballot(cand && slot != s0) == 0ull) {
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    if (m == 0ull) break;
+    const uint32_t fl = first_lane(m);
+    const uint32_t s0 = lane_value(slot, fl);
+    const uint64_t grp = __ballot(cand && slot == s0) & m;
     uint32_t base = 0u;
-    if (lane == fl) base = atomicAdd(&p.st[s0].n_cand, (uint32_t)__popcll(m));
+    if (lane == fl) base = atomicAdd(&p.st[s0].n_cand, (uint32_t)__popcll(grp));
     base = lane_value(base, fl);
-    if (cand) put_candidate(p, s0, base + (uint32_t)__popcll(m & lt), pa, pb, dd);
-  } else if (cand) {
-    put_candidate(p, slot, atomicAdd(&p.st[slot].n_cand, 1u), pa, pb, dd);
+    if ((grp >> lane) & 1ull) put_candidate(p, s0, base + (uint32_t)__popcll(grp & lt), pa, pb, dd);
+    m &= ~grp;
   }
+  if ((m >> lane) & 1ull) put_candidate(p, slot, atomicAdd(&p.st[slot].n_cand, 1u), pa, pb, dd);
 }
 
 // Narrow phase, stage 1: one lane per leaf pair.  The lane loads the leaf
