@@ -89,6 +89,9 @@ inline uint32_t round_cap_for(uint32_t seg, uint32_t nb) {
 // clamped minimum of one level per side.
 inline uint32_t min_segment(uint32_t budget, uint32_t nb) { return kSegSlack + 64u + budget / (nb ? nb : 1u); }
 
+constexpr uint32_t kBarGroups = 8;    // grid-barrier groups (the XCDs, when workgroups go round-robin)
+constexpr uint32_t kBarStride = 32;   // words between two groups' barrier words (128 bytes)
+
 // Control block of one persistent traversal launch.
 struct Ctl {
   uint32_t overflow;       // bit 0 front, bit 1 leaf pairs, bit 2 candidates, bit 3 spill stack
@@ -105,6 +108,10 @@ struct Ctl {
   unsigned long long trace_end;
   uint32_t trace_n[kTraceRounds];
   uint32_t trace_nl[kTraceRounds];
+  // two-level grid barrier: workgroup b arrives at group b % kBarGroups, whose
+  // counter and generation word each own a 128-byte line
+  uint32_t bar_grp[kBarGroups * kBarStride];
+  uint32_t bar_ggen[kBarGroups * kBarStride];
 };
 
 struct TravParams {

@@ -59,11 +59,18 @@ __device__ __forceinline__ void st_rlx(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide barrier for a cooperative launch.  The workgroup barrier orders
-// every wave's writes before thread 0's device-scope release; thread 0 then
-// arrives and waits with a bounded spin (a timeout raises `abort` so every
-// wave still reaches the end of the kernel) and acquires at device scope for
-// the whole workgroup before the closing workgroup barrier.
+// Grid-wide barrier for a cooperative launch, in two levels.  The workgroup
+// barrier orders every wave's writes before thread 0's device-scope release;
+// thread 0 then arrives at its group's counter (group = workgroup index mod
+// 8, the XCD of a round-robin placement); the last of a group resets that
+// counter and arrives at the top counter; the last group's leader publishes
+// the next generation in every group's word.  Thread 0 waits on its group's
+// word with a bounded spin (a timeout raises `abort` so every wave still
+// reaches the end of the kernel) and acquires at device scope for the whole
+// workgroup before the closing workgroup barrier.  One counter per group
+// instead of one for the grid: device-scope atomics on one word serialise at
+// tens of ns each, so 256 arrivals on one word cost several microseconds per
+// round, and 32 on each of eight words plus 8 on the top word a fraction.
 __device__ void grid_sync(Ctl* c, uint32_t spin_limit) {
   // every wave's stores have reached L2 (vmcnt counts stores on this target)
   // before the workgroup barrier, so thread 0's L2 writeback covers them
@@ -72,22 +79,38 @@ __device__ void grid_sync(Ctl* c, uint32_t spin_limit) {
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __builtin_amdgcn_s_waitcnt(0);
-    uint32_t gen = ld_rlx(&c->bar_gen);
-    // relaxed arrival: the release fence above already orders this
-    // workgroup's writes before it (each cache writeback and invalidate is a
-    // round's fixed cost, so every workgroup does one of each)
-    uint32_t arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == gridDim.x - 1) {
-      // the last arrival acquires every workgroup's release, then publishes
-      // the next generation (after the count reset) with a release store
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      st_rlx(&c->bar_count, 0u);
-      __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    const uint32_t groups = gridDim.x < kBarGroups ? gridDim.x : kBarGroups;
+    const uint32_t g = blockIdx.x % kBarGroups;
+    const uint32_t members = (gridDim.x - g + kBarGroups - 1u) / kBarGroups;
+    uint32_t* const gen_word = &c->bar_ggen[g * kBarStride];
+    const uint32_t gen = ld_rlx(gen_word);
+    // relaxed arrivals: the release fence above already orders this
+    // workgroup's writes before them (each cache writeback and invalidate is
+    // a round's fixed cost, so every workgroup does one of each)
+    const uint32_t arrived = __hip_atomic_fetch_add(&c->bar_grp[g * kBarStride], 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+    bool wait = true;
+    if (arrived == members - 1u) {
+      // the group's last arrival: every member has arrived (and no member can
+      // arrive again before the generation changes), so the counter resets;
+      // it acquires the members' releases and releases them upward
+      st_rlx(&c->bar_grp[g * kBarStride], 0u);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      const uint32_t top = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (top == groups - 1u) {
+        // the last group: acquire every group's release, reset, publish
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        st_rlx(&c->bar_count, 0u);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        for (uint32_t h = 0; h < groups; ++h) st_rlx(&c->bar_ggen[h * kBarStride], gen + 1u);
+        wait = false;
+      }
+    }
+    if (wait) {
       // relaxed polling: an acquire load here would invalidate L2 on every
       // poll; the single acquire fence below orders the reads that follow
       uint32_t spins = 0;
-      while (ld_rlx(&c->bar_gen) == gen) {
+      while (ld_rlx(gen_word) == gen) {
         __builtin_amdgcn_s_sleep(2);
         if (++spins > spin_limit) {
           st_rlx(&c->abort, 1u);
