@@ -1121,8 +1121,12 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   const uint32_t round0 = p.round0 + c->round_base;
 
   for (uint32_t r = 0; r < p.max_rounds; ++r) {
-    if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) break;
     const uint32_t round = round0 + r;     // global round: selects the buffer parity
+    // the round's control words, read together (one line of the control
+    // block): stop flags and the spill stack's height
+    const uint32_t c_abort = ld_rlx(&c->abort), c_ovf = ld_rlx(&c->overflow);
+    const uint32_t c_st = ld_rlx(&c->stack_top[round & 1u]);
+    if (c_abort || c_ovf) break;
     Round rd;
     rd.nb = gridDim.x + 1u;                // workgroup segments + the admission segment
     rd.seg_f = p.seg_front;
@@ -1133,9 +1137,11 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     rd.lin = p.leaf[round & 1u];
     rd.lout = p.leaf[(round + 1u) & 1u];
     rd.stk = p.stack;
-    if (lds_slots)
-      for (uint32_t s = tid; s < p.n_slots; s += kTravBlock) bs->best[s] = ld_rlx(&p.st[s].best);
-    // segment prefixes of this round's inputs: wave 0 the front, wave 1 the leaf pairs
+    // the slots' running bounds by waves 2.., at the same time as the segment
+    // prefixes of this round's inputs by wave 0 (the front) and wave 1 (the
+    // leaf pairs)
+    if (lds_slots && tid >= 128u)
+      for (uint32_t s = tid - 128u; s < p.n_slots; s += kTravBlock - 128u) bs->best[s] = ld_rlx(&p.st[s].best);
     if (wib == 0u) wave_prefix(p.fcount[round & 1u], rd.nb, bs->fpre, lane);
     else if (wib == 1u) wave_prefix(p.lcount[round & 1u], rd.nb, bs->lpre, lane);
     __syncthreads();
@@ -1146,7 +1152,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     // topped up from the stack's top (the most recently spilled, i.e. deepest
     // entries), so pending pairs are worked off depth-first in chunks.  Every
     // workgroup derives the same decision from the same counts.
-    rd.st = ld_rlx(&c->stack_top[round & 1u]);
+    rd.st = c_st;
     if (n == 0u && nl == 0u && rd.st == 0u) break;
     rd.n_in = n < p.round_cap ? n : p.round_cap;
     rd.n_spill = n - rd.n_in;
