@@ -85,6 +85,22 @@ def numpy_morton_order(mesh):
     return np.argsort(code, kind="stable")
 
 
+def tied_mesh(rng, n_same, n_other):
+    """n_same copies of one triangle (equal keys) interleaved with a soup: the
+    stable order keeps the copies in index order across tiles and passes."""
+    soup = g.random_soup(rng, n_other)
+    verts = np.concatenate([np.array([[0.1, 0.2, 0.3], [0.15, 0.2, 0.3], [0.1, 0.25, 0.3]], np.float32),
+                            soup.verts])
+    other = soup.tris.astype(np.int64) + 3
+    tris = np.zeros((n_same + n_other, 3), np.int64)
+    pos = np.sort(rng.choice(n_same + n_other, n_other, replace=False))
+    mask = np.zeros(n_same + n_other, bool)
+    mask[pos] = True
+    tris[mask] = other
+    tris[~mask] = [0, 1, 2]
+    return g.Mesh(verts, tris.astype(np.uint32))
+
+
 MESHES = {
     "one": lambda: g.Mesh(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32), np.array([[0, 1, 2]], np.uint32)),
     "three": lambda: g.random_soup(np.random.default_rng(3), 3),
@@ -93,6 +109,10 @@ MESHES = {
     "soup": lambda: g.random_soup(np.random.default_rng(5), 5000),
     "sphere": lambda: g.icosphere(9, 1.0, 1e-3, np.random.default_rng(2)),
     "height": lambda: g.heightfield(40, 0.02, np.random.default_rng(4)),
+    # several sort tiles (8,192 keys) and a ragged last tile
+    "soup100k": lambda: g.random_soup(np.random.default_rng(8), 100_003),
+    # 30,000 equal keys spread over five tiles among 5,000 others
+    "ties": lambda: tied_mesh(np.random.default_rng(9), 30_000, 5_000),
 }
 
 
@@ -112,14 +132,13 @@ def test_build_invariants(gctx, name):
     assert np.array_equal(e["tris"].reshape(n, 3, 3), m.verts[m.tris[orig]])
     boxes = e["boxes"]
     tris = e["tris"].reshape(n, 3, 3)
-    for j in range(L):                                               # leaf boxes: tight
-        s, t = (j * n) // L, ((j + 1) * n) // L
-        assert 1 <= t - s <= 2
-        pts = tris[s:t].reshape(-1, 3)
-        assert np.array_equal(boxes[L + j, :3], pts.min(0))
-        assert np.array_equal(boxes[L + j, 3:], pts.max(0))
-    for i in range(1, L):                                            # parent = union
-        l, r = boxes[2 * i], boxes[2 * i + 1]
-        assert np.array_equal(boxes[i, :3], np.minimum(l[:3], r[:3]))
-        assert np.array_equal(boxes[i, 3:], np.maximum(l[3:], r[3:]))
+    j = np.arange(L, dtype=np.int64)                                 # leaf boxes: tight
+    s0, s1 = (j * n) // L, ((j + 1) * n) // L
+    assert np.all((s1 - s0 >= 1) & (s1 - s0 <= 2))
+    tmin, tmax = tris.min(1), tris.max(1)
+    assert np.array_equal(boxes[L:2 * L, :3], np.minimum.reduceat(tmin, s0))
+    assert np.array_equal(boxes[L:2 * L, 3:], np.maximum.reduceat(tmax, s0))
+    i = np.arange(1, L)                                              # parent = union
+    assert np.array_equal(boxes[i, :3], np.minimum(boxes[2 * i, :3], boxes[2 * i + 1, :3]))
+    assert np.array_equal(boxes[i, 3:], np.maximum(boxes[2 * i, 3:], boxes[2 * i + 1, 3:]))
     assert np.array_equal(boxes[1, :3], m.verts[m.tris].reshape(-1, 3).min(0))
