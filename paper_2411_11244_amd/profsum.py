@@ -85,6 +85,7 @@ def counters(csvs, cmds: str, title: str) -> str:
     """Per-dispatch means of every counter in one or more ``--pmc`` runs, for
     the traversal kernel, with the derived utilisations computed from them."""
     vals = {}
+    res = {}   # launch resources of the traversal's dispatches, as the profiler records them
     for path in csvs:
         per = defaultdict(lambda: defaultdict(float))   # counter -> dispatch -> value
         names = {}
@@ -93,6 +94,9 @@ def counters(csvs, cmds: str, title: str) -> str:
                 d = r["Dispatch_Id"]
                 names[d] = r["Kernel_Name"]
                 per[r["Counter_Name"]][d] += float(r["Counter_Value"])
+                if TRAVERSE in r["Kernel_Name"] and not res:
+                    res = {k: r[k] for k in ("Scratch_Size", "VGPR_Count", "Accum_VGPR_Count", "SGPR_Count",
+                                             "LDS_Block_Size", "Workgroup_Size", "Grid_Size") if k in r}
         for cn, byd in per.items():
             tv = [v for d, v in byd.items() if TRAVERSE in names[d]]
             if tv:
@@ -126,6 +130,9 @@ def counters(csvs, cmds: str, title: str) -> str:
                     1.0 - v["TCP_TCC_READ_REQ_sum"] / max(1.0, v["TCP_TOTAL_CACHE_ACCESSES_sum"])))
     if der:
         out += ["", "| derived | value |", "|---|---|"] + [f"| {k} | {x:.4g} |" for k, x in der]
+    if res:
+        out += ["", "| k_traverse launch resource (profiler record) | value |", "|---|---|"]
+        out += [f"| {k} | {x} |" for k, x in res.items()]
     return "\n".join(out)
 
 
