@@ -196,7 +196,10 @@ gdist_status_t gdist_set_allocator(gdist_ctx_t ctx, void* (*alloc)(size_t, void*
  * emit, level reduction; Sec. 6.3).  The caller's arrays are copied; the
  * handle owns its device data until gdist_release.  Zero-area triangles are
  * accepted.  E_INVALID: n_tris == 0 or >= 2^31, n_verts == 0, an index >=
- * n_verts, or a non-finite vertex coordinate.  Synchronous. */
+ * n_verts, or a non-finite vertex coordinate (checked on the device, reported
+ * after the build's one host wait; nothing is kept).  E_DEVICE: a HIP error,
+ * or a bounded wait of the sort's look-back gave up (nothing is kept).
+ * Synchronous. */
 gdist_status_t gdist_build(gdist_ctx_t ctx, const float* verts, uint32_t n_verts,
                            const uint32_t* tris, uint32_t n_tris, uint32_t flags,
                            gdist_mesh_t* out);
