@@ -27,7 +27,8 @@
  *   - Triangle indices in results are the caller's original 0-based indices.
  *   - Points in results are in the world frame, FP64.
  *   - A context is bound to one device and is not thread-safe: calls on one
- *     context must not overlap.  Distinct contexts may be used concurrently.
+ *     context must not overlap.  Distinct contexts may be used concurrently
+ *     (gdist_build calls on one device take turns inside the library).
  */
 #ifndef GDIST_H
 #define GDIST_H

@@ -9,6 +9,8 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -817,6 +819,18 @@ gdist_status_t gdist_set_option(gdist_ctx_t c, const char* key, double v) {
   return fail(GDIST_E_INVALID, "unknown option '%s'", key);
 }
 
+// One build at a time per device in this process.  The sort's look-back
+// waits only for tiles of its own launch, which the dispatcher places in
+// index order; two sort launches from different streams on one device could
+// interleave their placement so that each waits on a tile the other keeps
+// from being placed (the bounded wait would then fail the build).
+static std::mutex& build_mutex(int device) {
+  static std::mutex guard;
+  static std::map<int, std::mutex> per_device;
+  std::lock_guard<std::mutex> lk(guard);
+  return per_device[device];
+}
+
 gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const uint32_t* tris, uint32_t nt,
                            uint32_t flags, gdist_mesh_t* out) {
   if (!c) return fail(GDIST_E_HANDLE, "NULL context");
@@ -829,6 +843,7 @@ gdist_status_t gdist_build(gdist_ctx_t c, const float* verts, uint32_t nv, const
   if (nv == 0) return fail(GDIST_E_INVALID, "n_verts = 0");
   if (flags & ~(GDIST_BUILD_DEVICE_PTR | GDIST_BUILD_DEFORMABLE))
     return fail(GDIST_E_INVALID, "unknown build flags 0x%x", flags);
+  std::lock_guard<std::mutex> build_lock(build_mutex(c->device));
   HIPCHK(hipSetDevice(c->device));
   const bool dev = (flags & GDIST_BUILD_DEVICE_PTR) != 0;
   const bool deformable = (flags & GDIST_BUILD_DEFORMABLE) != 0;

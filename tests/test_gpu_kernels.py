@@ -142,3 +142,40 @@ def test_build_invariants(gctx, name):
     assert np.array_equal(boxes[i, :3], np.minimum(boxes[2 * i, :3], boxes[2 * i + 1, :3]))
     assert np.array_equal(boxes[i, 3:], np.maximum(boxes[2 * i, 3:], boxes[2 * i + 1, 3:]))
     assert np.array_equal(boxes[1, :3], m.verts[m.tris].reshape(-1, 3).min(0))
+
+
+def test_concurrent_builds_two_contexts():
+    """Builds on two contexts from two threads at once (the library takes them
+    in turns per device) give the same trees as a build alone."""
+    import threading
+    m = MESHES["soup100k"]()
+    ctxs = [gdist.gdist_create(0) for _ in range(2)]
+    out, errs = [None, None], []
+
+    def run(i):
+        try:
+            orders = []
+            for _ in range(3):
+                h = gdist.gdist_build(ctxs[i], m.verts, m.tris)
+                e = gdist.gdist_mesh_export(ctxs[i], h)
+                orders.append((e["orig"].copy(), e["boxes"].copy()))
+                gdist.gdist_release(ctxs[i], h)
+            out[i] = orders
+        except Exception as ex:   # reported below
+            errs.append(ex)
+
+    try:
+        ts = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        assert not errs, errs
+        ref = numpy_morton_order(m)
+        for orders in out:
+            for orig, boxes in orders:
+                assert np.array_equal(orig.astype(np.int64), ref)
+                assert np.array_equal(boxes, out[0][0][1])
+    finally:
+        for c in ctxs:
+            gdist.gdist_destroy(c)
