@@ -1276,6 +1276,16 @@ __device__ __forceinline__ ReevalRange reeval_range(const TravParams& p, uint32_
   return r;
 }
 
+// Smallest (take_min) or largest 64-bit value over the wave (every lane active).
+__device__ __forceinline__ unsigned long long wave_extreme_u64(unsigned long long v, bool take_min) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(v, o, kWave);
+    v = take_min ? (w < v ? w : v) : (w > v ? w : v);
+  }
+  return v;
+}
+
 __global__ __launch_bounds__(kTravThreads) void k_reeval_values(TravParams p, uint32_t G) {
   Ctl* c = p.ctl;
   if (ld_rlx(&c->abort) || ld_rlx(&c->overflow)) return;
@@ -1286,13 +1296,20 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_values(TravParams p, ui
   const Cand* cands = p.cand + (uint64_t)rr.slot * p.cand_per_slot;
   double* d64 = p.cand_d64 + (uint64_t)rr.slot * p.cand_per_slot;
   const float best = bitsf(ld_rlx(&st.best));
+  const bool mn = d.mode == 0;
+  // per-thread extremes and counts, reduced over the wave into one atomic per
+  // word (every thread of the workgroup serves the same slot; an atomic per
+  // candidate on one slot's words serialises when a query has many)
+  float b32 = mn ? __builtin_huge_valf() : 0.f;
+  unsigned long long kd = mn ? ~0ull : 0ull;
+  uint32_t seen = 0u, nadm = 0u;
   for (uint32_t i = rr.begin; i < rr.end; i += rr.stride) {
     Cand cd = cands[i];
     // the FP32 optimum over the tested triangle pairs is the best candidate
     // value (max mode tests its pairs in the filter, which keeps no optimum)
-    if (d.mode == 0) atomicMin(&st.best32, fbits(cd.d32));
-    else atomicMax(&st.best32, fbits(cd.d32));
-    const bool adm = d.mode == 0 ? (cd.d32 - st.delta <= best) : (cd.d32 + st.delta >= best);
+    b32 = mn ? fminf(b32, cd.d32) : fmaxf(b32, cd.d32);
+    ++seen;
+    const bool adm = mn ? (cd.d32 - st.delta <= best) : (cd.d32 + st.delta >= best);
     if (!adm) {
       d64[i] = -1.0;
       continue;
@@ -1300,14 +1317,27 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_values(TravParams p, ui
     V3<double> P[3], Q[3];
     world_tri(d.trisA, cd.ia, d.RA, d.tA, P);
     world_tri(d.trisB, cd.ib, d.RB, d.tB, Q);
-    double d2 = d.mode == 0 ? tri_tri_min_d2<double, false>(P, Q, nullptr, nullptr)
-                            : tri_tri_max_d2<double, false>(P, Q, nullptr, nullptr);
+    double d2 = mn ? tri_tri_min_d2<double, false>(P, Q, nullptr, nullptr)
+                   : tri_tri_max_d2<double, false>(P, Q, nullptr, nullptr);
     double dd = sqrt(d2);
     d64[i] = dd;
-    unsigned long long b = (unsigned long long)__double_as_longlong(dd);
-    if (d.mode == 0) atomicMin(&st.key_d, b);
-    else atomicMax(&st.key_d, b);
-    atomicAdd(&st.n_admitted, 1u);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(dd);   // ordered: dd >= 0
+    kd = mn ? (b < kd ? b : kd) : (b > kd ? b : kd);
+    ++nadm;
+  }
+  const uint32_t wseen = wave_sum(seen), wadm = wave_sum(nadm);
+  const float wb = mn ? wave_min(b32) : wave_max(b32);
+  kd = wave_extreme_u64(kd, mn);
+  if (threadIdx.x % kWave == 0u) {
+    if (wseen) {
+      if (mn) atomicMin(&st.best32, fbits(wb));
+      else atomicMax(&st.best32, fbits(wb));
+    }
+    if (wadm) {
+      if (mn) atomicMin(&st.key_d, kd);
+      else atomicMax(&st.key_d, kd);
+      atomicAdd(&st.n_admitted, wadm);
+    }
   }
 }
 
@@ -1327,13 +1357,22 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_ties(TravParams p, uint
   const Cand* cands = p.cand + (uint64_t)rr.slot * p.cand_per_slot;
   const double* d64 = p.cand_d64 + (uint64_t)rr.slot * p.cand_per_slot;
   const double D = __longlong_as_double((long long)st.key_d);
+  unsigned long long kp = ~0ull;   // smallest tied caller pair and tie count of this thread
+  uint32_t nt = 0u;
   for (uint32_t i = rr.begin; i < rr.end; i += rr.stride) {
     double dd = d64[i];
     if (dd < 0.0) continue;
     if (fabs(dd - D) <= d.tau) {
-      atomicMin(&st.key_pair, caller_pair(d, cands[i]));
-      atomicAdd(&st.n_ties, 1u);
+      const unsigned long long k = caller_pair(d, cands[i]);
+      kp = k < kp ? k : kp;
+      ++nt;
     }
+  }
+  const uint32_t wnt = wave_sum(nt);
+  kp = wave_extreme_u64(kp, true);
+  if (threadIdx.x % kWave == 0u && wnt) {
+    atomicMin(&st.key_pair, kp);
+    atomicAdd(&st.n_ties, wnt);
   }
 }
 
