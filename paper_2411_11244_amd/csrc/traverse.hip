@@ -465,6 +465,20 @@ __global__ __launch_bounds__(kTravThreads) void k_admit(TravParams p) {
 // offset) through an exclusive prefix sum over the workgroups' counts.
 constexpr uint32_t kMaxBlocks = 1023;   // segments (+ admission) fit the 1024-point search
 constexpr uint32_t kLdsSlots = 512;
+constexpr uint32_t kLdsDesc = 256;      // launches of at most this many slots keep their fields in LDS
+
+// The per-slot descriptor fields the expansion and the narrow phase read, kept
+// in LDS for the whole launch (a wave whose lanes belong to several queries
+// would otherwise gather them per lane from global memory, a dependent round
+// trip before every box and triangle load).
+struct SlotLds {
+  const float* boxA;
+  const float* boxB;
+  const float* trisA;
+  const float* trisB;
+  uint32_t mode, depthA, depthB, LA, LB, nA, nB, enh, xfA, pad[3];
+  Xf32 T;
+};
 
 struct BlockState {
   uint32_t fpre[kMaxBlocks + 2];   // prefix of the current front's segment counts
@@ -473,6 +487,7 @@ struct BlockState {
   uint32_t best[kLdsSlots];        // per-slot running bound (float bits), refreshed each round
   float delta[kLdsSlots];
   unsigned long long stats[ST_N];
+  SlotLds sd[kLdsDesc];            // when n_slots <= kLdsDesc
 };
 
 struct Round {
@@ -546,6 +561,25 @@ struct SlotView {
 };
 __device__ __forceinline__ void fill_view(const TravParams& p, const BlockState* bs, bool lds, uint32_t slot,
                                           SlotView& v) {
+  if (p.n_slots <= kLdsDesc) {
+    const SlotLds& d = bs->sd[slot];
+    v.boxA = d.boxA;
+    v.boxB = d.boxB;
+    v.trisA = d.trisA;
+    v.trisB = d.trisB;
+    v.mode = d.mode;
+    v.depthA = d.depthA;
+    v.depthB = d.depthB;
+    v.LA = d.LA;
+    v.LB = d.LB;
+    v.nA = d.nA;
+    v.nB = d.nB;
+    v.enh = d.enh;
+    v.xfA = d.xfA;
+    v.delta = get_delta(p, bs, lds, slot);
+    v.best = get_best(p, bs, lds, slot);
+    return;
+  }
   const SlotDesc& d = p.desc[slot];
   v.boxA = d.boxA;
   v.boxB = d.boxB;
@@ -959,14 +993,14 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
   }
   V3<float> P[2][3], Q[2][3];
   if (act) {
-    const Xf32& T = p.desc[slot].T;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       float a[9], b[9];
       const uint32_t ia = sa + i < ea ? sa + i : sa;
       const uint32_t ib = sb + i < eb ? sb + i : sb;
       load_tri_a(v.trisA, v.xfA != 0u, p.desc[slot].TA, ia, a);
-      load_tri_xf(v.trisB, ib, T, b);
+      if (p.n_slots <= kLdsDesc) load_tri_xf(v.trisB, ib, bs->sd[slot].T, b);
+      else load_tri_xf(v.trisB, ib, p.desc[slot].T, b);
 #pragma unroll
       for (int w = 0; w < 3; ++w) {
         P[i][w] = mk<float>(a[3 * w], a[3 * w + 1], a[3 * w + 2]);
@@ -1048,7 +1082,8 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
     {
       float a[9], b[9];
       load_tri_a(v.trisA, v.xfA != 0u, p.desc[slot].TA, pa, a);
-      load_tri_xf(v.trisB, pb, p.desc[slot].T, b);
+      if (p.n_slots <= kLdsDesc) load_tri_xf(v.trisB, pb, bs->sd[slot].T, b);
+      else load_tri_xf(v.trisB, pb, p.desc[slot].T, b);
 #pragma unroll
       for (int w = 0; w < 3; ++w) {
         P[w] = mk<float>(a[3 * w], a[3 * w + 1], a[3 * w + 2]);
@@ -1116,6 +1151,25 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   }
   if (lds_slots)
     for (uint32_t s = tid; s < p.n_slots; s += kTravBlock) bs->delta[s] = p.st[s].delta;
+  if (p.n_slots <= kLdsDesc)
+    for (uint32_t s = tid; s < p.n_slots; s += kTravBlock) {
+      const SlotDesc& d = p.desc[s];
+      SlotLds& o = bs->sd[s];
+      o.boxA = d.boxA;
+      o.boxB = d.boxB;
+      o.trisA = d.trisA;
+      o.trisB = d.trisB;
+      o.mode = d.mode;
+      o.depthA = d.depthA;
+      o.depthB = d.depthB;
+      o.LA = d.LA;
+      o.LB = d.LB;
+      o.nA = d.nA;
+      o.nB = d.nB;
+      o.enh = d.enhanced;
+      o.xfA = d.xfA;
+      o.T = d.T;
+    }
   // nothing in this launch writes round_base (the next stepped launch's base
   // is advanced by a later kernel)
   const uint32_t round0 = p.round0 + c->round_base;
