@@ -820,29 +820,39 @@ __device__ __forceinline__ void eval_child(const SlotView& v, bool valid, const 
 // swap places in commutative sums, minima and maxima), so every child pair is
 // evaluated as (G box, S box) whichever side G is, with no branch on the
 // split: lanes of one wave may split differently.
+// Input entry rb + lane of a k = 1 round (the front's first n_in entries,
+// then popped stack entries); a lane past n_ent gets a dummy entry.
+__device__ __forceinline__ uint4 entry_row(const BlockState* bs, const Round& rd, uint32_t rb, uint32_t n_ent,
+                                           uint32_t lane) {
+  const uint32_t ei = rb + lane;
+  uint4 e = make_uint4(1u, 1u, 0u, 0u);
+  if (rb < n_ent) {
+    const uint32_t elast = n_ent - 1u < rb + 63u ? n_ent - 1u : rb + 63u;
+    const bool act = ei < n_ent;
+    if (rb < rd.n_in) {
+      const uint32_t fend = elast < rd.n_in ? elast : rd.n_in - 1u;
+      const uint32_t addr = row_addr(bs->fpre, rd.nb, rd.seg_f, rb, fend, ei < rd.n_in ? ei : fend, lane);
+      if (act) e = ei < rd.n_in ? rd.fin[addr] : rd.stk[(uint64_t)rd.pop_base + (ei - rd.n_in)];
+    } else if (act) {
+      e = rd.stk[(uint64_t)rd.pop_base + (ei - rd.n_in)];
+    }
+  }
+  return e;
+}
+
+// pre: the first row's entries, already loaded (one task ahead), or nullptr.
 template <int R, bool ON>
 __device__ __forceinline__ void expand_entries(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base0,
                                                uint32_t n_ent, uint32_t lane, uint64_t lt, WaveStats<ON>& ws,
-                                               LaneStats<ON>& ls) {
+                                               LaneStats<ON>& ls, const uint4* pre) {
   Ctl* c = p.ctl;
   uint4 ent[R];
   bool act[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const uint32_t rb = base0 + 64u * r;
-    const uint32_t ei = rb + lane;
-    act[r] = ei < n_ent;
-    ent[r] = make_uint4(1u, 1u, 0u, 0u);
-    if (rb < n_ent) {
-      const uint32_t elast = n_ent - 1u < rb + 63u ? n_ent - 1u : rb + 63u;
-      if (rb < rd.n_in) {
-        const uint32_t fend = elast < rd.n_in ? elast : rd.n_in - 1u;
-        const uint32_t addr = row_addr(bs->fpre, rd.nb, rd.seg_f, rb, fend, ei < rd.n_in ? ei : fend, lane);
-        if (act[r]) ent[r] = ei < rd.n_in ? rd.fin[addr] : rd.stk[(uint64_t)rd.pop_base + (ei - rd.n_in)];
-      } else if (act[r]) {
-        ent[r] = rd.stk[(uint64_t)rd.pop_base + (ei - rd.n_in)];
-      }
-    }
+    act[r] = rb + lane < n_ent;
+    ent[r] = (r == 0 && pre) ? *pre : entry_row(bs, rd, rb, n_ent, lane);
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -1241,18 +1251,23 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     // expansion work is handed out in groups of `rows` waves' worth of items
     const uint32_t total = spill_end + (uint32_t)(((uint64_t)exp_items + 64u * rows - 1u) / (64u * rows));
     uint32_t qn = 0;  // wave-uniform fill of this wave's LDS queue
-    // a leaf task's entries are loaded one task ahead, so their latency
-    // overlaps the previous task's triangle loads
-    uint4 lent = gw < leaf_waves ? leaf_row(bs, rd, gw * 64u, nl, lane) : make_uint4(1u, 1u, 0u, 0u);
+    // a leaf task's entries, and a k = 1 expansion task's, are loaded one
+    // task ahead, so their latency overlaps the previous task's work
+    auto row_of = [&](uint32_t ww) -> uint4 {   // ww is wave-uniform
+      if (ww < leaf_waves) return leaf_row(bs, rd, ww * 64u, nl, lane);
+      if (by_entry && ww >= spill_end && ww < total)
+        return entry_row(bs, rd, (ww - spill_end) * 64u * kEntRows, exp_items, lane);
+      return make_uint4(1u, 1u, 0u, 0u);
+    };
+    uint4 pre = row_of(gw);
     for (uint32_t w = gw;;) {
       const bool more = w < total;
       if (more) {
-        if (w < leaf_waves) {
-          const uint4 cur = lent;
-          if (w + nw < leaf_waves) lent = leaf_row(bs, rd, (w + nw) * 64u, nl, lane);
-          narrow_filter_wave(p, bs, rd, w * 64u, nl, cur, lane, lt, q, qn, ws, ls);
-        } else if (w < spill_end) spill_wave(bs, rd, (w - leaf_waves) * 64u, lane);
-        else if (by_entry) expand_entries<kEntRows>(p, bs, rd, (w - spill_end) * 64u * kEntRows, exp_items, lane, lt, ws, ls);
+        const uint4 cur = pre;
+        if (w + nw < total) pre = row_of(w + nw);
+        if (w < leaf_waves) narrow_filter_wave(p, bs, rd, w * 64u, nl, cur, lane, lt, q, qn, ws, ls);
+        else if (w < spill_end) spill_wave(bs, rd, (w - leaf_waves) * 64u, lane);
+        else if (by_entry) expand_entries<kEntRows>(p, bs, rd, (w - spill_end) * 64u * kEntRows, exp_items, lane, lt, ws, ls, &cur);
         else expand_rows<kRows>(p, bs, rd, (w - spill_end) * 64u * kRows, exp_items, kk, lane, lt, ws, ls);
         w += nw;
       }
