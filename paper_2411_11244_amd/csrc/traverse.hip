@@ -961,6 +961,55 @@ __device__ __forceinline__ void add_candidates(const TravParams& p, bool cand, u
   if ((m >> lane) & 1ull) put_candidate(p, slot, atomicAdd(&p.st[slot].n_cand, 1u), pa, pb, dd);
 }
 
+// Candidates of the exact stage wait in the wave's LDS buffer cb (cbn of
+// kCandBuf entries, wave-uniform) instead of taking their places in memory
+// one group at a time: a query whose bound falls slowly produces many
+// candidates that the final bound no longer admits, and every append is an
+// atomic on the same counter, which serialises across the device.  A full
+// buffer is first pruned against the slots' current bounds (a bound only
+// tightens, so an entry it no longer admits can never be needed again), and
+// only flushed if that frees too little; the launch flushes the rest at its
+// end, pruned against the bounds in memory, so the FP64 stage (a later
+// launch) sees every candidate the final window can hold.
+constexpr uint32_t kCandBuf = 128;
+__device__ __forceinline__ void prune_cands(const TravParams& p, const BlockState* bs, bool lds, bool fresh, Cand* cb,
+                                            uint32_t& cbn, uint32_t lane, uint64_t lt) {
+  uint32_t kept = 0u;   // rows are compacted in order, so a write never lands on an unread entry
+#pragma unroll 1
+  for (uint32_t r0 = 0u; r0 < cbn; r0 += 64u) {
+    const uint32_t i = r0 + lane;
+    bool k = i < cbn;
+    const Cand e = cb[k ? i : 0u];
+    if (k) {
+      const uint32_t s = e.slot;
+      const uint32_t mode = p.n_slots <= kLdsDesc ? bs->sd[s].mode : p.desc[s].mode;
+      const float best = fresh ? bitsf(ld_rlx(&p.st[s].best)) : get_best(p, bs, lds, s);
+      const float delta = get_delta(p, bs, lds, s);
+      k = mode == 0 ? e.d32 - delta <= best : e.d32 + delta >= best;
+    }
+    const uint64_t m = __ballot(k);
+    __builtin_amdgcn_wave_barrier();
+    if (k) cb[kept + (uint32_t)__popcll(m & lt)] = e;
+    __builtin_amdgcn_wave_barrier();
+    kept += (uint32_t)__popcll(m);
+  }
+  cbn = kept;
+}
+template <bool ON>
+__device__ __forceinline__ void flush_cands(const TravParams& p, Cand* cb, uint32_t& cbn, uint32_t lane, uint64_t lt,
+                                            WaveStats<ON>& ws) {
+#pragma unroll 1
+  for (uint32_t r0 = 0u; r0 < cbn; r0 += 64u) {
+    const uint32_t i = r0 + lane;
+    const bool a = i < cbn;
+    const Cand e = cb[a ? i : 0u];
+    add_candidates(p, a, e.slot, e.ia, e.ib, e.d32, lane, lt);
+    add_stat(ws, ST_CAND, a);
+  }
+  __builtin_amdgcn_wave_barrier();
+  cbn = 0u;
+}
+
 // Narrow phase, stage 1: one lane per leaf pair.  The lane loads the leaf
 // pair's 1-2 triangles of each side once.  Min mode: each of the (up to 4)
 // triangle pairs gets the cheap separating-axis test, and the survivors go
@@ -1080,7 +1129,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
 // (the filter queues min-mode pairs only).
 template <bool ON>
 __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs, bool lds, uint4 e, bool act,
-                                            uint32_t lane, uint64_t lt, WaveStats<ON>& ws) {
+                                            uint32_t lane, uint64_t lt, Cand* cb, uint32_t& cbn, WaveStats<ON>& ws) {
   const uint32_t slot = e.x, pa = e.y, pb = e.z;
   const SlotView v = slot_view(p, bs, lds, act, slot);
   const uint32_t mode = v.mode;
@@ -1112,8 +1161,24 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
     }
   }
   add_stat(ws, ST_FULL, act);
-  add_candidates(p, act && cand, slot, pa, pb, dd, lane, lt);
-  add_stat(ws, ST_CAND, act && cand);
+  const uint64_t cm = __ballot(act && cand);
+  if (cm) {
+    const uint32_t nc = (uint32_t)__popcll(cm);
+    if (cbn + nc > kCandBuf) {
+      prune_cands(p, bs, lds, false, cb, cbn, lane, lt);
+      if (cbn + nc > kCandBuf) flush_cands(p, cb, cbn, lane, lt, ws);
+    }
+    if (act && cand) {
+      Cand ce;
+      ce.d32 = dd;
+      ce.slot = slot;
+      ce.ia = pa;
+      ce.ib = pb;
+      cb[cbn + (uint32_t)__popcll(cm & lt)] = ce;
+    }
+    __builtin_amdgcn_wave_barrier();
+    cbn += nc;
+  }
   improve_best(p, bs, lds, act, slot, mode, improve, lane);
   improve_bound(&p.st[0].best32, sizeof(SlotState) / 4, act, slot, mode, dd, lane);
 }
@@ -1138,6 +1203,7 @@ template <bool LDS_SLOTS, bool STATS>
 __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   __shared__ BlockState bs_;
   __shared__ uint4 sq[kTravWaves][kQueue];
+  __shared__ Cand scb[kTravWaves][kCandBuf];
   BlockState* bs = &bs_;
   Ctl* c = p.ctl;
   const uint32_t tid = threadIdx.x;
@@ -1147,6 +1213,8 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
   const uint32_t gw = blockIdx.x * kTravWaves + wib;
   const uint32_t nw = gridDim.x * kTravWaves;
   uint4* q = sq[wib];
+  Cand* cb = scb[wib];
+  uint32_t cbn = 0u;   // wave-uniform fill of cb
   constexpr bool lds_slots = LDS_SLOTS;
   WaveStats<STATS> ws;
 #pragma unroll
@@ -1277,7 +1345,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
         const bool a = lane < take;
         const uint4 e = q[qn + (a ? lane : 0u)];
         __builtin_amdgcn_wave_barrier();
-        narrow_full(p, bs, lds_slots, e, a, lane, lt, ws);
+        narrow_full(p, bs, lds_slots, e, a, lane, lt, cb, cbn, ws);
       }
       if (!more) break;
     }
@@ -1306,6 +1374,10 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
       bs->lo = 0u;
     }
     grid_sync(c, p.spin_limit);
+  }
+  if (cbn) {   // the buffered candidates the bounds in memory still admit
+    prune_cands(p, bs, lds_slots, true, cb, cbn, lane, lt);
+    if (cbn) flush_cands(p, cb, cbn, lane, lt, ws);
   }
   if (blockIdx.x == 0 && tid == 0) {
     c->trace_end = (unsigned long long)wall_clock64();
