@@ -1180,7 +1180,8 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
     cbn += nc;
   }
   improve_best(p, bs, lds, act, slot, mode, improve, lane);
-  improve_bound(&p.st[0].best32, sizeof(SlotState) / 4, act, slot, mode, dd, lane);
+  // (the FP32 optimum, best32, is taken by the FP64 stage as the extreme over
+  // the candidates: the optimal pair is always one, so nothing is kept here)
 }
 
 __device__ __forceinline__ void world_tri(const float* tris, uint32_t pos, const double* R, const double* t,

@@ -11,6 +11,12 @@ locality of the trees' boxes in the caches.
 
     python -m paper_2411_11244_amd.tune --out tune.json   (needs the GPU)
     python -m paper_2411_11244_amd.tune --workload batched --out batched.json
+    python -m paper_2411_11244_amd.tune --workload hard_min --out hard_min.json
+
+The hard_min workload is the min-distance query between the two concentric
+noisy spheres of 1,997,120 triangles each, where the front peaks near 1.7e7
+entries: its sweep includes front buffers large enough to expand that front
+in one round.
 
 For the serving core it sweeps the server's slots ("max_slots") and rounds
 per step ("rounds_per_step") together with the context options above on the
@@ -131,7 +137,7 @@ def tune_server(ctx: int, handles: List[int], burst, paced, grid: Dict[str, Iter
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="rings", choices=["rings", "tiny", "batched", "serving"])
+    ap.add_argument("--workload", default="rings", choices=["rings", "tiny", "batched", "hard_min", "serving"])
     ap.add_argument("--frames", type=int, default=100)
     ap.add_argument("--out", default="")
     ap.add_argument("--reps", type=int, default=3)
@@ -168,6 +174,13 @@ def main():
             descs.append(gdist.make_desc(ha, hb, pa, pb, 0))
         grid = {"expand_budget": [1 << 18, 1 << 20, 1 << 22], "k_cap": [4, 6, 8], "blocks_per_cu": [0],
                 "front_capacity": [1 << 26], "group_size": [0]}
+    elif args.workload == "hard_min":
+        w = g.hard(seed=4, n=316)
+        hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in w.meshes]
+        q = w.queries[0]
+        descs = [gdist.make_desc(hs[q.a], hs[q.b], q.pose_a, q.pose_b, q.mode)]
+        grid = {"expand_budget": [1 << 20, 1 << 22, 1 << 24], "k_cap": [6, 8], "blocks_per_cu": [0],
+                "front_capacity": [1 << 26, 1 << 27], "group_size": [0]}
     else:
         if args.workload == "rings":
             w = g.rings(frames=args.frames)
