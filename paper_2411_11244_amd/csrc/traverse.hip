@@ -969,10 +969,13 @@ __device__ __forceinline__ void add_candidates(const TravParams& p, bool cand, u
 // buffer is first pruned against the slots' current bounds (a bound only
 // tightens, so an entry it no longer admits can never be needed again), and
 // only flushed if that frees too little; the launch flushes the rest at its
-// end, pruned against the bounds in memory, so the FP64 stage (a later
-// launch) sees every candidate the final window can hold.
+// end, so the FP64 stage (a later launch) sees every candidate the final
+// window can hold.  The last prune reads the workgroup's copy of the bounds,
+// refreshed at the start of the round that found no work (the final bounds,
+// then) or of the launch's last round (a stepped launch), instead of a load
+// per wave of one word in memory.
 constexpr uint32_t kCandBuf = 128;
-__device__ __forceinline__ void prune_cands(const TravParams& p, const BlockState* bs, bool lds, bool fresh, Cand* cb,
+__device__ __forceinline__ void prune_cands(const TravParams& p, const BlockState* bs, bool lds, Cand* cb,
                                             uint32_t& cbn, uint32_t lane, uint64_t lt) {
   uint32_t kept = 0u;   // rows are compacted in order, so a write never lands on an unread entry
 #pragma unroll 1
@@ -983,7 +986,7 @@ __device__ __forceinline__ void prune_cands(const TravParams& p, const BlockStat
     if (k) {
       const uint32_t s = e.slot;
       const uint32_t mode = p.n_slots <= kLdsDesc ? bs->sd[s].mode : p.desc[s].mode;
-      const float best = fresh ? bitsf(ld_rlx(&p.st[s].best)) : get_best(p, bs, lds, s);
+      const float best = get_best(p, bs, lds, s);
       const float delta = get_delta(p, bs, lds, s);
       k = mode == 0 ? e.d32 - delta <= best : e.d32 + delta >= best;
     }
@@ -1165,7 +1168,7 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
   if (cm) {
     const uint32_t nc = (uint32_t)__popcll(cm);
     if (cbn + nc > kCandBuf) {
-      prune_cands(p, bs, lds, false, cb, cbn, lane, lt);
+      prune_cands(p, bs, lds, cb, cbn, lane, lt);
       if (cbn + nc > kCandBuf) flush_cands(p, cb, cbn, lane, lt, ws);
     }
     if (act && cand) {
@@ -1377,7 +1380,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
     grid_sync(c, p.spin_limit);
   }
   if (cbn) {   // the buffered candidates the bounds in memory still admit
-    prune_cands(p, bs, lds_slots, true, cb, cbn, lane, lt);
+    prune_cands(p, bs, lds_slots, cb, cbn, lane, lt);
     if (cbn) flush_cands(p, cb, cbn, lane, lt, ws);
   }
   if (blockIdx.x == 0 && tid == 0) {
