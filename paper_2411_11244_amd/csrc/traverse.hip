@@ -1182,7 +1182,10 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
     __builtin_amdgcn_wave_barrier();
     cbn += nc;
   }
-  improve_best(p, bs, lds, act, slot, mode, improve, lane);
+  // only a value that beats the bound this lane already saw can help (the
+  // others would cost a device-scope load of a word every wave reads)
+  const bool helps = act && (mode == 0 ? improve < v.best : improve > v.best);
+  improve_best(p, bs, lds, helps, slot, mode, improve, lane);
   // (the FP32 optimum, best32, is taken by the FP64 stage as the extreme over
   // the candidates: the optimal pair is always one, so nothing is kept here)
 }
