@@ -961,11 +961,13 @@ __device__ __forceinline__ void add_candidates(const TravParams& p, bool cand, u
   if ((m >> lane) & 1ull) put_candidate(p, slot, atomicAdd(&p.st[slot].n_cand, 1u), pa, pb, dd);
 }
 
-// Candidates of the exact stage wait in the wave's LDS buffer cb (cbn of
-// kCandBuf entries, wave-uniform) instead of taking their places in memory
-// one group at a time: a query whose bound falls slowly produces many
-// candidates that the final bound no longer admits, and every append is an
-// atomic on the same counter, which serialises across the device.  A full
+// Candidates (pairs whose FP32 value lies inside the window of the slot's
+// bound: from the exact stage in min mode, from the filter in max mode) wait
+// in the wave's LDS buffer cb (cbn of kCandBuf entries, wave-uniform) instead
+// of taking their places in memory one group at a time: a query whose bound
+// moves slowly produces many candidates that the final bound no longer
+// admits, and every append is an atomic on the same counter, which
+// serialises across the device.  A full
 // buffer is first pruned against the slots' current bounds (a bound only
 // tightens, so an entry it no longer admits can never be needed again), and
 // only flushed if that frees too little; the launch flushes the rest at its
@@ -1012,6 +1014,30 @@ __device__ __forceinline__ void flush_cands(const TravParams& p, Cand* cb, uint3
   __builtin_amdgcn_wave_barrier();
   cbn = 0u;
 }
+// Put the lanes' candidates (those with `cand` set) into the wave's buffer,
+// making room first if they do not fit.
+template <bool ON>
+__device__ __forceinline__ void buffer_cands(const TravParams& p, const BlockState* bs, bool lds, bool cand,
+                                             uint32_t slot, uint32_t pa, uint32_t pb, float dd, uint32_t lane,
+                                             uint64_t lt, Cand* cb, uint32_t& cbn, WaveStats<ON>& ws) {
+  const uint64_t cm = __ballot(cand);
+  if (cm == 0ull) return;
+  const uint32_t nc = (uint32_t)__popcll(cm);
+  if (cbn + nc > kCandBuf) {
+    prune_cands(p, bs, lds, cb, cbn, lane, lt);
+    if (cbn + nc > kCandBuf) flush_cands(p, cb, cbn, lane, lt, ws);
+  }
+  if (cand) {
+    Cand ce;
+    ce.d32 = dd;
+    ce.slot = slot;
+    ce.ia = pa;
+    ce.ib = pb;
+    cb[cbn + (uint32_t)__popcll(cm & lt)] = ce;
+  }
+  __builtin_amdgcn_wave_barrier();
+  cbn += nc;
+}
 
 // Narrow phase, stage 1: one lane per leaf pair.  The lane loads the leaf
 // pair's 1-2 triangles of each side once.  Min mode: each of the (up to 4)
@@ -1038,7 +1064,8 @@ __device__ __forceinline__ uint4 leaf_row(const BlockState* bs, const Round& rd,
 template <bool ON>
 __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockState* bs, const Round& rd, uint32_t base,
                                                    uint32_t n_items, uint4 ent, uint32_t lane, uint64_t lt, uint4* q,
-                                                   uint32_t& qn, WaveStats<ON>& ws, LaneStats<ON>& ls) {
+                                                   uint32_t& qn, Cand* cb, uint32_t& cbn, WaveStats<ON>& ws,
+                                                   LaneStats<ON>& ls) {
   bool act = base + lane < n_items;
   const uint32_t slot = ent.w;
   const SlotView v = slot_view(p, bs, rd.lds_slots, act, slot);
@@ -1116,9 +1143,28 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
         imp = fmaxf(imp, fmaxf(dd - delta, 0.f));
         cand = dd + delta >= best;
       }
-      add_candidates(p, cand, slot, pa, pb, dd, lane, lt);
+      // into the wave's candidate buffer while it has room, else straight to
+      // memory (no pruning here: that code stays out of the filter)
+      const uint64_t cm = __ballot(cand);
+      if (cm) {
+        const uint32_t nc = (uint32_t)__popcll(cm);
+        if (cbn + nc <= kCandBuf) {
+          if (cand) {
+            Cand ce;
+            ce.d32 = dd;
+            ce.slot = slot;
+            ce.ia = pa;
+            ce.ib = pb;
+            cb[cbn + (uint32_t)__popcll(cm & lt)] = ce;
+          }
+          __builtin_amdgcn_wave_barrier();
+          cbn += nc;
+        } else {
+          add_candidates(p, cand, slot, pa, pb, dd, lane, lt);
+          add_stat(ws, ST_CAND, cand);
+        }
+      }
       add_stat(ws, ST_FULL, full);
-      add_stat(ws, ST_CAND, cand);
     }
     uint64_t m = __ballot(pass);
     if (pass) q[qn + (uint32_t)__popcll(m & lt)] = make_uint4(slot, pa, pb, 0u);
@@ -1164,24 +1210,7 @@ __device__ __forceinline__ void narrow_full(const TravParams& p, BlockState* bs,
     }
   }
   add_stat(ws, ST_FULL, act);
-  const uint64_t cm = __ballot(act && cand);
-  if (cm) {
-    const uint32_t nc = (uint32_t)__popcll(cm);
-    if (cbn + nc > kCandBuf) {
-      prune_cands(p, bs, lds, cb, cbn, lane, lt);
-      if (cbn + nc > kCandBuf) flush_cands(p, cb, cbn, lane, lt, ws);
-    }
-    if (act && cand) {
-      Cand ce;
-      ce.d32 = dd;
-      ce.slot = slot;
-      ce.ia = pa;
-      ce.ib = pb;
-      cb[cbn + (uint32_t)__popcll(cm & lt)] = ce;
-    }
-    __builtin_amdgcn_wave_barrier();
-    cbn += nc;
-  }
+  buffer_cands(p, bs, lds, act && cand, slot, pa, pb, dd, lane, lt, cb, cbn, ws);
   // only a value that beats the bound this lane already saw can help (the
   // others would cost a device-scope load of a word every wave reads)
   const bool helps = act && (mode == 0 ? improve < v.best : improve > v.best);
@@ -1340,7 +1369,7 @@ __global__ __launch_bounds__(kTravBlock) void k_traverse(TravParams p) {
       if (more) {
         const uint4 cur = pre;
         if (w + nw < total) pre = row_of(w + nw);
-        if (w < leaf_waves) narrow_filter_wave(p, bs, rd, w * 64u, nl, cur, lane, lt, q, qn, ws, ls);
+        if (w < leaf_waves) narrow_filter_wave(p, bs, rd, w * 64u, nl, cur, lane, lt, q, qn, cb, cbn, ws, ls);
         else if (w < spill_end) spill_wave(bs, rd, (w - leaf_waves) * 64u, lane);
         else if (by_entry) expand_entries<kEntRows>(p, bs, rd, (w - spill_end) * 64u * kEntRows, exp_items, lane, lt, ws, ls, &cur);
         else expand_rows<kRows>(p, bs, rd, (w - spill_end) * 64u * kRows, exp_items, kk, lane, lt, ws, ls);
@@ -1535,8 +1564,10 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_report(TravParams p, ui
   const Cand* cands = p.cand + (uint64_t)rr.slot * p.cand_per_slot;
   const double* d64 = p.cand_d64 + (uint64_t)rr.slot * p.cand_per_slot;
   gdist_result_t& res = p.res[rr.slot];
+  const double D = __longlong_as_double((long long)st.key_d);
   for (uint32_t i = rr.begin; i < rr.end; i += rr.stride) {
-    if (d64[i] < 0.0) continue;
+    const double dd = d64[i];
+    if (dd < 0.0 || !(fabs(dd - D) <= d.tau)) continue;   // only a tie can be the reported pair
     const Cand cd = cands[i];
     unsigned long long key = caller_pair(d, cd);
     if (key != st.key_pair) continue;
@@ -1564,7 +1595,6 @@ __global__ __launch_bounds__(kTravThreads) void k_reeval_report(TravParams p, ui
       res.status = GDIST_E_DEVICE;
       res.distance = __longlong_as_double(0x7ff8000000000000ll);
     } else {
-      double D = __longlong_as_double((long long)st.key_d);
       res.distance = D;
       res.status = GDIST_OK;
       res.flags = (st.n_ties > 1u ? GDIST_F_TIED : 0u) | ((d.mode == 0 && D == 0.0) ? GDIST_F_ZERO : 0u);
