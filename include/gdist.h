@@ -180,6 +180,12 @@ gdist_status_t gdist_destroy(gdist_ctx_t ctx);
  *                     triangle pairs, bytes); 0 = they do not (a few per cent
  *                     faster; those fields then read 0, rounds and the front
  *                     peak are still counted).  Results do not change.
+ *   "cand_buffer"     candidates each wave holds in its LDS buffer before they
+ *                     go to memory (0..128, default 128; 0 = every candidate
+ *                     goes to memory at once).  A full buffer is pruned
+ *                     against the query's current bound, then flushed.
+ *                     Results do not change (small values exercise the
+ *                     pruning and flushing paths).
  */
 gdist_status_t gdist_set_option(gdist_ctx_t ctx, const char* key, double value);
 

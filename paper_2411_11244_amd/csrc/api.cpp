@@ -234,6 +234,7 @@ gdist_status_t traverse_group(gdist_ctx* c, uint32_t g0, uint32_t gn, gdist_resu
     TravParams p;
     std::memset(&p, 0, sizeof(p));
     p.stats = c->stats;
+    p.cand_buf = c->cand_buf;
     p.desc = (const SlotDesc*)c->desc.p + g0;
     p.st = (SlotState*)c->st.p + g0;
     p.res = (gdist_result_t*)c->res.p + g0;
@@ -795,6 +796,7 @@ gdist_status_t gdist_set_option(gdist_ctx_t c, const char* key, double v) {
   if (k == "bounds") return u32opt(&c->bounds, 0, 1);
   if (k == "one_to_many") return u32opt(&c->one_to_many, 0, 2);
   if (k == "stats") return u32opt(&c->stats, 0, 1);
+  if (k == "cand_buffer") return u32opt(&c->cand_buf, 0, kCandBuf);
   if (k == "warm_start") {
     gdist_status_t st = u32opt(&c->warm_start, 0, 1);
     if (st == GDIST_OK && !c->warm_start) c->warm.clear();

@@ -111,6 +111,7 @@ struct gdist_ctx {
   };
   std::unordered_map<uint64_t, std::vector<WorldTree>> world;
   uint32_t stats = 1;                      // 1: traversals count their work statistics
+  uint32_t cand_buf = gd::kCandBuf;        // per-wave candidate buffer capacity used (<= kCandBuf)
   uint32_t one_to_many = 1;                // 0: pairwise refits, 1: shared refit when it refits less, 2: shared
   unsigned long long last_ctl_sum[gd::ST_N] = {};
   gdist_stats_t last{};

@@ -72,6 +72,9 @@ enum StatIdx {
 };
 
 constexpr uint32_t kTraceRounds = 48;
+// Entries of a traversal wave's LDS candidate buffer (the "cand_buffer"
+// option sets how many of them are used).
+constexpr uint32_t kCandBuf = 128;
 // A traversal workgroup appends at most its even share of a round's work items
 // plus kSegSlack (its waves' last, partial task group); segments are sized
 // from this so that the front and leaf-pair buffers cannot overflow.
@@ -143,6 +146,7 @@ struct TravParams {
   const uint32_t* finish;  // re-evaluation over slots 0 .. n_list-1 where finish[slot] == 1
                            //   (nullptr: every listed slot)
   uint32_t stats;          // 1: count the work statistics (ST_*; rounds and the peak always)
+  uint32_t cand_buf;       // candidates a wave keeps in LDS before they go to memory (0..128)
 };
 
 // Head of the report of one serving step (device buffer, copied to pinned

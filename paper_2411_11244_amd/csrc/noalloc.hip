@@ -130,6 +130,7 @@ gdist_status_t run_query_noalloc(gdist_ctx* c, const gdist_query_desc_t& q, gdis
   TravParams p;
   std::memset(&p, 0, sizeof(p));
   p.stats = c->stats;
+  p.cand_buf = c->cand_buf;
   p.desc = (const SlotDesc*)(base + lay.desc);
   p.st = (SlotState*)(base + lay.st);
   p.res = (gdist_result_t*)(base + lay.res);

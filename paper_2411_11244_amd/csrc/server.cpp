@@ -101,6 +101,7 @@ TravParams params(gdist_server* sv) {
   std::memset(&p, 0, sizeof(p));
   gdist_ctx* c = sv->c;
   p.stats = c->stats;
+  p.cand_buf = c->cand_buf;
   p.desc = (const SlotDesc*)sv->desc.p;
   p.st = (SlotState*)sv->st.p;
   p.res = (gdist_result_t*)((char*)sv->rep.p + sv->res_off);

@@ -963,7 +963,8 @@ __device__ __forceinline__ void add_candidates(const TravParams& p, bool cand, u
 
 // Candidates (pairs whose FP32 value lies inside the window of the slot's
 // bound: from the exact stage in min mode, from the filter in max mode) wait
-// in the wave's LDS buffer cb (cbn of kCandBuf entries, wave-uniform) instead
+// in the wave's LDS buffer cb (cbn of at most p.cand_buf <= kCandBuf entries,
+// wave-uniform) instead
 // of taking their places in memory one group at a time: a query whose bound
 // moves slowly produces many candidates that the final bound no longer
 // admits, and every append is an atomic on the same counter, which
@@ -976,7 +977,6 @@ __device__ __forceinline__ void add_candidates(const TravParams& p, bool cand, u
 // refreshed at the start of the round that found no work (the final bounds,
 // then) or of the launch's last round (a stepped launch), instead of a load
 // per wave of one word in memory.
-constexpr uint32_t kCandBuf = 128;
 __device__ __forceinline__ void prune_cands(const TravParams& p, const BlockState* bs, bool lds, Cand* cb,
                                             uint32_t& cbn, uint32_t lane, uint64_t lt) {
   uint32_t kept = 0u;   // rows are compacted in order, so a write never lands on an unread entry
@@ -1023,9 +1023,14 @@ __device__ __forceinline__ void buffer_cands(const TravParams& p, const BlockSta
   const uint64_t cm = __ballot(cand);
   if (cm == 0ull) return;
   const uint32_t nc = (uint32_t)__popcll(cm);
-  if (cbn + nc > kCandBuf) {
+  if (cbn + nc > p.cand_buf) {
     prune_cands(p, bs, lds, cb, cbn, lane, lt);
-    if (cbn + nc > kCandBuf) flush_cands(p, cb, cbn, lane, lt, ws);
+    if (cbn + nc > p.cand_buf) flush_cands(p, cb, cbn, lane, lt, ws);
+    if (nc > p.cand_buf) {   // a buffer smaller than the wave's candidates
+      add_candidates(p, cand, slot, pa, pb, dd, lane, lt);
+      add_stat(ws, ST_CAND, cand);
+      return;
+    }
   }
   if (cand) {
     Cand ce;
@@ -1148,7 +1153,7 @@ __device__ __forceinline__ void narrow_filter_wave(const TravParams& p, BlockSta
       const uint64_t cm = __ballot(cand);
       if (cm) {
         const uint32_t nc = (uint32_t)__popcll(cm);
-        if (cbn + nc <= kCandBuf) {
+        if (cbn + nc <= p.cand_buf) {
           if (cand) {
             Cand ce;
             ce.d32 = dd;

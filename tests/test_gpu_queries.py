@@ -533,3 +533,62 @@ def test_stats_off_same_results(orc):
             gdist.gdist_set_option(ctx, "stats", 2)
     finally:
         gdist.gdist_destroy(ctx)
+
+
+def test_cand_buffer_sizes_same_results(orc):
+    """Candidates wait in a per-wave LDS buffer ("cand_buffer" entries) that
+    is pruned against the query's current bound when full, then flushed, and
+    flushed at the end of every launch; 0 sends each candidate to memory at
+    once.  Small buffers force the pruning and flushing paths on every wave
+    that finds candidates: every size gives the same results, and the
+    near-coincident spheres (many candidates in both modes) and the 36-way tie
+    still equal the oracle."""
+    rng = np.random.default_rng(41)
+    meshes = [g.random_mesh_of_size(rng, t) for t in (600, 4000, 12000)]
+    sa = g.icosphere(30, 1.0, 2e-5, rng)
+    sb = g.icosphere(30, 1.0001, 2e-5, rng)
+    tie = g.tiny(3, identity_rotation=True)
+    descs = []
+    for i in range(12):
+        a, b = (int(x) for x in rng.integers(0, len(meshes), size=2))
+        gap = [-0.05, 2e-3, 0.1][i % 3]
+        pa, pb = g.place_with_gap(rng, meshes[a], meshes[b], gap, g.random_rotation(rng), g.random_rotation(rng))
+        descs.append((a, b, pa, pb, i % 2))
+    I = g.identity_pose()
+    rb = (g.random_rotation(rng), np.zeros(3))
+    tq = tie.queries[0]
+    out = {}
+    for nb in (128, 64, 8, 1, 0):
+        ctx = gdist.gdist_create(0)
+        try:
+            gdist.gdist_set_option(ctx, "cand_buffer", nb)
+            hs = [build(ctx, m) for m in meshes] + [build(ctx, sa), build(ctx, sb), build(ctx, tie.meshes[0])]
+            qs = [gdist.make_desc(hs[a], hs[b], pa, pb, m) for a, b, pa, pb, m in descs]
+            qs += [gdist.make_desc(hs[3], hs[4], I, rb, m) for m in (0, 1)]
+            res = gdist.gdist_query_batch(ctx, qs)
+            res += [gdist.gdist_query(ctx, hs[3], hs[4], I, rb, m) for m in (0, 1)]
+            res.append(gdist.gdist_query(ctx, hs[5], hs[5], tq.pose_a, tq.pose_b, 0))
+            out[nb] = res
+        finally:
+            gdist.gdist_destroy(ctx)
+    with pytest.raises(gdist.GdistError):
+        ctx = gdist.gdist_create(0)
+        try:
+            gdist.gdist_set_option(ctx, "cand_buffer", 129)
+        finally:
+            gdist.gdist_destroy(ctx)
+    ref = out[128]
+    for nb, res in out.items():
+        for x, y in zip(ref, res):
+            assert x["status"] == 0 and y["status"] == 0, (nb, x, y)
+            assert x["distance"] == y["distance"], (nb, x["distance"], y["distance"])
+            assert (x["tri_a"], x["tri_b"], x["n_ties"]) == (y["tri_a"], y["tri_b"], y["n_ties"]), nb
+            assert np.array_equal(x["point_a"], y["point_a"]) and np.array_equal(x["point_b"], y["point_b"])
+    for k, m in enumerate((0, 1)):
+        ref_o = oracle_query(orc, sa, I, sb, rb, m, "bvh")
+        check_against_oracle(orc, ref[12 + k], ref_o, sa, I, sb, rb, m)
+        assert ref[14 + k]["distance"] == ref[12 + k]["distance"]
+    m = tie.meshes[0]
+    ref_t = oracle_query(orc, m, tq.pose_a, m, tq.pose_b, 0, "brute")
+    assert ref[16]["n_ties"] == 36
+    assert (ref[16]["tri_a"], ref[16]["tri_b"]) == (ref_t["tri_a"], ref_t["tri_b"])
