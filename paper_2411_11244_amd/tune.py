@@ -151,7 +151,7 @@ def main():
         ctx = gdist.gdist_create(0)
         gdist.gdist_set_option(ctx, "stats", 0)   # timed as served: diagnostic counters off
         hs = [gdist.gdist_build(ctx, m.verts, m.tris) for m in pool]
-        grid = {"max_slots": [64, 128, 256], "rounds_per_step": [4, 8], "expand_budget": [1 << 18, 1 << 22],
+        grid = {"max_slots": [64, 128, 256], "rounds_per_step": [4, 8, 16], "expand_budget": [1 << 18, 1 << 22],
                 "k_cap": [5, 8]}
         t = time.time()
         res = tune_server(ctx, hs, burst, paced, grid)
