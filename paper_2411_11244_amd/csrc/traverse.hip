@@ -131,7 +131,8 @@ __device__ __forceinline__ uint32_t first_lane(uint64_t m) { return (uint32_t)__
 // issues one atomic, only if that improves the bound; lanes of further slots
 // issue one each.  (Waves of batched calls mix slots; one atomic per lane on
 // the word of a busy slot serialises.)  lds_copy, if set, is this workgroup's
-// LDS copy of the bounds, updated the same way.
+// LDS copy of the bounds, updated the same way and with the value read from
+// memory.
 __device__ __forceinline__ void improve_bound(uint32_t* target_base, size_t stride_words, bool act, uint32_t slot,
                                               uint32_t mode, float v, uint32_t lane, uint32_t* lds_copy = nullptr) {
   uint64_t am = __ballot(act);
@@ -148,12 +149,15 @@ __device__ __forceinline__ void improve_bound(uint32_t* target_base, size_t stri
     r = m0 == 0 ? wave_min(r) : wave_max(r);
     if (lane == fl) {
       uint32_t* t = target_base + stride_words * s0;
+      // the bound in memory, read to skip an atomic that cannot help, also
+      // tightens the workgroup's copy (other workgroups' progress this round)
+      const uint32_t g = ld_rlx(t);
       if (m0 == 0) {
-        if (fbits(r) < ld_rlx(t)) atomicMin(t, fbits(r));
-        if (lds_copy) atomicMin(&lds_copy[s0], fbits(r));
+        if (fbits(r) < g) atomicMin(t, fbits(r));
+        if (lds_copy) atomicMin(&lds_copy[s0], fbits(r) < g ? fbits(r) : g);
       } else {
-        if (fbits(r) > ld_rlx(t)) atomicMax(t, fbits(r));
-        if (lds_copy) atomicMax(&lds_copy[s0], fbits(r));
+        if (fbits(r) > g) atomicMax(t, fbits(r));
+        if (lds_copy) atomicMax(&lds_copy[s0], fbits(r) > g ? fbits(r) : g);
       }
     }
     am &= ~grp;
