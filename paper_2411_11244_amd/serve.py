@@ -16,6 +16,7 @@ All distance work runs in libgdist.so; this file only schedules submissions.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import time
 from typing import List, Sequence
@@ -33,14 +34,20 @@ def run_stream(ctx: int, handles: Sequence[int], queries, max_slots: int = 64, r
     every completion.  Returns {"results": [dict per query, in query order],
     "latency_ms": np.ndarray, "wall_s": float, "stats": server stats}.
     ``direct`` launches each step's kernels one by one instead of replaying
-    the step graph."""
+    the step graph.  Python's cyclic garbage collector is off while the
+    stream runs: a collection pause (tens of ms once the results pile up)
+    would hold back the arrivals due meanwhile and submit them as one burst,
+    a queueing delay made by the driver, not the server."""
     srv = gdist.gdist_server_start(ctx, max_slots, rounds_per_step, front_capacity, cand_per_slot, 0,
                                    stack_capacity, gdist.GDIST_SERVER_DIRECT if direct else 0)
     n = len(queries)
     results: List[dict] = [None] * n  # type: ignore
     got = 0
+    gc_on = gc.isenabled()
     try:
         descs = [gdist.make_desc(handles[q.a], handles[q.b], q.pose_a, q.pose_b, q.mode) for q in queries]
+        gc.collect()
+        gc.disable()
         t0 = time.perf_counter()
         nxt = 0
         deadline = t0 + timeout_s
@@ -59,6 +66,8 @@ def run_stream(ctx: int, handles: Sequence[int], queries, max_slots: int = 64, r
         wall = time.perf_counter() - t0
         stats = gdist.gdist_server_stats(srv)
     finally:
+        if gc_on:
+            gc.enable()
         gdist.gdist_server_stop(srv)
     lat = np.array([(r["t_done_ns"] - r["t_submit_ns"]) * 1e-6 for r in results])
     return {"results": results, "latency_ms": lat, "wall_s": wall, "stats": stats}
@@ -69,11 +78,24 @@ def run_plain_stream(ctx: int, handles: Sequence[int], queries, time_scale: floa
     """The plain form under the same open-loop arrivals: one gdist_query per
     query, issued at its arrival time (or as soon as the previous call
     returns, if that is later).  Latency = completion - arrival, so it
-    includes the time a query waited behind earlier ones.  Returns
+    includes the time a query waited behind earlier ones.  As in run_stream,
+    Python's cyclic garbage collector is off while the stream runs.  Returns
     {"results", "latency_ms", "wall_s"}."""
     n = len(queries)
     results: List[dict] = []
     lat = np.zeros(n)
+    gc.collect()
+    gc_on = gc.isenabled()
+    gc.disable()
+    try:
+        return _plain_stream(ctx, handles, queries, time_scale, timeout_s, results, lat)
+    finally:
+        if gc_on:
+            gc.enable()
+
+
+def _plain_stream(ctx, handles, queries, time_scale, timeout_s, results, lat) -> dict:
+    n = len(queries)
     t0 = time.perf_counter()
     deadline = t0 + timeout_s
     for i, q in enumerate(queries):
