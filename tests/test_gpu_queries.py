@@ -592,3 +592,37 @@ def test_cand_buffer_sizes_same_results(orc):
     ref_t = oracle_query(orc, m, tq.pose_a, m, tq.pose_b, 0, "brute")
     assert ref[16]["n_ties"] == 36
     assert (ref[16]["tri_a"], ref[16]["tri_b"]) == (ref_t["tri_a"], ref_t["tri_b"])
+
+
+def test_work_counters_and_byte_counts(gctx):
+    """The traversal's work statistics obey the structure of the method and
+    the byte counts are the algorithmic-byte formulas over them: 16 B per
+    popped entry, 24 B per child box read (2^kA + 2^kB of them per popped
+    entry, at least 3) and 16 B per pushed entry; 16 B per leaf pair and 36 B
+    per triangle read (1-2 per side and leaf pair); 144 B per candidate."""
+    rng = np.random.default_rng(53)
+    meshes = [g.random_mesh_of_size(rng, t) for t in (2000, 7000)]
+    hs = [build(gctx, m) for m in meshes]
+    try:
+        descs = []
+        for i in range(8):
+            a, b = i % 2, (i // 2) % 2
+            pa, pb = g.place_with_gap(rng, meshes[a], meshes[b], [1e-3, 0.05][i % 2], g.random_rotation(rng),
+                                      g.random_rotation(rng))
+            descs.append(gdist.make_desc(hs[a], hs[b], pa, pb, i % 2))
+        gdist.gdist_set_option(gctx, "stats", 1)
+        gdist.gdist_query_batch(gctx, descs)
+        st = gdist.gdist_last_stats(gctx)
+    finally:
+        for h in hs:
+            gdist.gdist_release(gctx, h)
+    assert st["entries_popped"] > 0 and st["leaf_pairs"] > 0 and st["candidates"] > 0
+    assert st["bytes_traversal"] == 16 * st["entries_popped"] + 24 * st["child_boxes"] + 16 * st["entries_pushed"]
+    assert st["bytes_narrow"] == 16 * st["leaf_pairs"] + 36 * st["leaf_tris"]
+    assert st["bytes_reeval"] == 144 * st["candidates"]
+    assert 3 * st["entries_popped"] <= st["child_boxes"]
+    assert st["entries_pushed"] <= st["child_pairs"]
+    assert 2 * st["leaf_pairs"] <= st["leaf_tris"] <= 4 * st["leaf_pairs"]
+    assert st["leaf_pairs"] <= st["tri_pairs"] <= 4 * st["leaf_pairs"]
+    assert st["tri_full"] <= st["tri_pairs"]
+    assert st["rounds"] > 0 and st["front_peak"] > 0
